@@ -1,0 +1,59 @@
+"""Pins of the seeded input generators (shared by the oracle side and the GPU side)."""
+import numpy as np
+import pytest
+
+import tomo_inputs as ti
+from tests import refs
+
+
+def test_philox_known_answers():
+    """Known-answer vectors published with the Random123 reference implementation of
+    Philox4x32-10 (Salmon et al., SC'11)."""
+    cases = [
+        ((0, 0, 0, 0), (0, 0), (0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8)),
+        ((0xFFFFFFFF,) * 4, (0xFFFFFFFF,) * 2, (0x408F276D, 0x41C83B0E, 0xA20BC7C6, 0x6D5451FD)),
+        ((0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344), (0xA4093822, 0x299F31D0),
+         (0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1)),
+    ]
+    for ctr, key, want in cases:
+        got = ti.philox4x32_10(*ctr, *key)
+        assert tuple(int(v) for v in got) == want
+
+
+def test_philox_counts_range_and_uniformity():
+    c = ti.philox_counts_rows(10, 20240, np.arange(200))
+    assert c.dtype == np.uint16 and c.shape == (200, 1024)
+    assert c.min() == 0 and c.max() == 12
+    freq = np.bincount(c.ravel(), minlength=13) / c.size
+    assert np.max(np.abs(freq - 1 / 13)) < 0.005
+
+
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_born_probabilities_match_explicit_projectors(n):
+    rng = np.random.default_rng(50 + n)
+    psi = ti.haar_state(n, rng)
+    p = ti.born_probs_pure(n, psi)
+    np.testing.assert_allclose(p, refs.born_from_projectors(n, np.outer(psi, psi.conj())),
+                               rtol=0, atol=1e-14)
+    G = ti.ginibre_factor(n, 3, rng)
+    np.testing.assert_allclose(ti.born_probs_mixed(n, G),
+                               refs.born_from_projectors(n, G @ G.conj().T), rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("n,p_dep", [(2, 0.0), (3, 0.05)])
+def test_ghz_probabilities(n, p_dep):
+    p = ti.ghz_probs(n, p_dep)
+    np.testing.assert_allclose(p, refs.born_from_projectors(n, refs.ghz_density(n, p_dep)),
+                               rtol=0, atol=1e-14)
+    lo = ti.ghz_probs(n, p_dep, 2, 7)
+    np.testing.assert_array_equal(lo, p[2:7])
+    with pytest.raises(ValueError):
+        ti.ghz_probs(n, p_dep, 0, 3 ** n + 1)
+
+
+def test_multinomial_rows_sum_to_shots():
+    rng = np.random.default_rng(3)
+    p = ti.born_probs_pure(4, ti.haar_state(4, rng))
+    shots = rng.integers(100, 10_000, size=81)
+    c = ti.multinomial_counts(p, shots, rng)
+    assert np.array_equal(c.sum(axis=1), shots)
