@@ -1,0 +1,273 @@
+#!/usr/bin/env python3
+"""Benchmark of the LRE hot path (steps (i) + (ii)) on one MI355X.
+
+Default workload: n = 14 qubits, 3^14 = 4,782,969 Pauli bases x 2^14 outcomes of
+uint16 counts (156.7 GB, resident in HBM before timing), generated on the device
+from Philox4x32-10 (i.i.d. uniform on {0..12}) with per-basis totals N_b; outputs
+the 4^14 binary64 Pauli coefficients and the 16384 x 16384 complex128 matrix mu.
+One step = one lre_estimate call (every kernel of steps (i) and (ii)).
+
+Prints ONE JSON line with throughput (counts/s over the whole step), the roofline of
+the dominant kernel (the counts pass) measured live with HIP events on the stream it
+runs on, and the CPU oracle timed on a bounded sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload n14|n12|n8]
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "counts/sec + end-to-end LRE time at n=12,14; int8-MFMA vs plain, exact sums"
+HBM_PEAK_GBS = 8000.0
+SEED14 = 0x16020860414
+
+
+def _hip():
+    lib = ctypes.CDLL("libamdhip64.so")
+    lib.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+    lib.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+    lib.hipEventDestroy.argtypes = [ctypes.c_void_p]
+    lib.hipEventSynchronize.argtypes = [ctypes.c_void_p]
+    return lib
+
+
+class StageEvents:
+    """4 HIP events per timed step, recorded by the library at stage boundaries."""
+
+    def __init__(self, steps):
+        self.hip = _hip()
+        self.ev = []
+        for _ in range(steps):
+            row = []
+            for _ in range(4):
+                e = ctypes.c_void_p()
+                if self.hip.hipEventCreate(ctypes.byref(e)) != 0:
+                    raise RuntimeError("hipEventCreate failed")
+                row.append(e.value)
+            self.ev.append(row)
+
+    def ms(self, step, a, b):
+        out = ctypes.c_float()
+        self.hip.hipEventSynchronize(ctypes.c_void_p(self.ev[step][b]))
+        rc = self.hip.hipEventElapsedTime(ctypes.byref(out), ctypes.c_void_p(self.ev[step][a]),
+                                          ctypes.c_void_p(self.ev[step][b]))
+        if rc != 0:
+            raise RuntimeError(f"hipEventElapsedTime failed ({rc})")
+        return float(out.value)
+
+    def close(self):
+        for row in self.ev:
+            for e in row:
+                self.hip.hipEventDestroy(ctypes.c_void_p(e))
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for rel in ("paper_1602_08604_amd/csrc/lre_kernels.hpp", "paper_1602_08604_amd/csrc/lre_abi.hip"):
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload):
+    """HBM bytes per counts-pass launch from the committed rocprofv3 PMC summary, if it was
+    taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_fold_counts_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def make_workload(name, torch):
+    import tomo_inputs.gpu as tg
+    dev = "cuda:0"
+    if name == "n14":
+        n = 14
+        counts, nb = tg.philox_counts(n, SEED14, device=dev)
+        desc = ("n=14: 4782969 bases x 16384 outcomes uint16 (156.7 GB in HBM), Philox4x32-10 "
+                "i.i.d. U{0..12}, per-basis totals N_b; coef f64 [4^14] + rho c128 [16384^2]")
+        return n, counts, 0, nb, desc
+    if name == "n12":
+        n = 12
+        counts = tg.ghz_multinomial_counts(n, 0.05, 10_000, seed=16021, device=dev)
+        desc = ("n=12: 531441 bases x 4096 outcomes uint16 (4.35 GB in HBM), GHZ_12 with "
+                "depolarising p=0.05, multinomial 10^4 shots/basis; coef f64 [4^12] + rho c128 [4096^2]")
+        return n, counts, 10_000, None, desc
+    if name == "n8":
+        import numpy as np
+        import tomo_inputs as ti
+        n = 8
+        rng = np.random.default_rng(16041)
+        G = ti.ginibre_factor(n, 4, rng)
+        c = ti.multinomial_counts(ti.born_probs_mixed(n, G), 10_000, rng)
+        desc = ("n=8: 6561 bases x 256 outcomes uint16, rank-4 Ginibre state, multinomial 10^4 "
+                "shots/basis; coef f64 [4^8] + rho c128 [256^2]")
+        return n, torch.from_numpy(c).to(dev), 10_000, None, desc
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(workload, n, shots, counts_dev, coef_dev, budget_s=12.0):
+    """Time the CPU oracle (as it stands) on a bounded sample of the same workload and
+    extrapolate to the whole step: step (i) visits 12^n (projector, coefficient) terms,
+    step (ii) 8^n (coefficient, entry) terms."""
+    import numpy as np
+
+    import oracle
+    import tomo_inputs as ti
+    rng = np.random.default_rng(7)
+    visits_i = 0
+    t_i = 0.0
+    coef = None
+    ncoef = 0
+    if workload == "n14":
+        t_end = time.time() + budget_s * 0.75
+        while time.time() < t_end:
+            # coefficients with few identity letters (<= 4): at most 81 compatible bases each
+            letters = rng.integers(1, 4, size=n)
+            letters[rng.choice(n, size=int(rng.integers(0, 5)), replace=False)] = 0
+            i = int(sum(int(a) * 4 ** (n - 1 - k) for k, a in enumerate(letters)))
+            bases = oracle.compatible_bases(n, i)
+            rows, nb = ti.philox_counts_rows_fast(n, SEED14, bases)      # input generation
+            t0 = time.perf_counter()
+            oracle.coef_from_rows(n, i, rows, nb)
+            t_i += time.perf_counter() - t0
+            visits_i += len(bases) * 2 ** n
+            ncoef += 1
+        sample = f"{ncoef} coefficients (<= 81 bases each) regenerated by the C Philox twin"
+        threads = 1
+    else:
+        c = counts_dev.cpu().numpy()
+        idx = rng.integers(0, 4 ** n, size=4096)
+        w = np.array([sum(1 for k in range(n) if (int(j) >> (2 * k)) & 3) for j in idx])
+        t0 = time.perf_counter()
+        oracle.coefs(n, c, shots, idx=idx)
+        t_i = time.perf_counter() - t0
+        visits_i = int(np.sum(3.0 ** (n - w))) * 2 ** n
+        sample = f"4096 random coefficients of the full count tensor"
+        threads = os.cpu_count()
+    # step (ii): sampled entries of eq. (4) on the GPU coefficients
+    coef = coef_dev.cpu().numpy() if workload != "n14" else None
+    t_ii, visits_ii = 0.0, 0
+    if coef is not None:
+        r = rng.integers(0, 2 ** n, 2000)
+        cc = rng.integers(0, 2 ** n, 2000)
+        t0 = time.perf_counter()
+        oracle.rho(n, coef, r, cc)
+        t_ii = time.perf_counter() - t0
+        visits_ii = 2000 * 2 ** n
+    rate_i = visits_i / t_i
+    t_full = 12.0 ** n / rate_i
+    if visits_ii:
+        t_full += 8.0 ** n / (visits_ii / t_ii)
+    else:
+        t_full += 8.0 ** n / rate_i  # same inner-loop cost per visited term
+    return {"value": 6.0 ** n / t_full, "unit": "counts/s", "cores": threads, "kind": "oracle",
+            "sample": f"{sample}; oracle time {t_i + t_ii:.1f} s, extrapolated to the whole "
+                      f"step ({t_full / 3600:.3g} h for 12^n + 8^n terms)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="n14", choices=["n14", "n12", "n8"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is a design note only)", file=sys.stderr)
+        raise SystemExit(2)
+
+    import torch
+    from paper_1602_08604_amd import lre
+
+    torch.cuda.set_device(0)
+    t_gen = time.time()
+    n, counts, shots, nb, desc = make_workload(args.workload, torch)
+    torch.cuda.synchronize()
+    t_gen = time.time() - t_gen
+    d = 1 << n
+    coef = torch.empty(4 ** n, dtype=torch.float64, device="cuda:0")
+    rho = torch.empty((d, d), dtype=torch.complex128, device="cuda:0")
+    ws = torch.empty(lre.workspace_bytes(n, shots, 0), dtype=torch.uint8, device="cuda:0")
+    print(f"[bench] workload {args.workload}: generated in {t_gen:.1f} s; workspace "
+          f"{ws.numel() / 1e9:.2f} GB", file=sys.stderr, flush=True)
+
+    def step():
+        lre.estimate(counts, shots, n_per_basis=nb, coef=coef, rho=rho, workspace=ws, check=False)
+
+    for _ in range(args.warmup):
+        step()
+    lre.check_flags("cuda:0")
+    ev = StageEvents(args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        lre.set_stage_events(ev.ev[k])
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lre.set_stage_events(None)
+    lre.check_flags("cuda:0")
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    pass1 = [ev.ms(k, 0, 1) for k in range(args.steps)]
+    step_i = [ev.ms(k, 0, 2) for k in range(args.steps)]
+    step_ii = [ev.ms(k, 2, 3) for k in range(args.steps)]
+    ev.close()
+    print(f"[bench] {args.steps} steps: {ms_step:.3f} ms/step wall; counts pass "
+          f"{sum(pass1) / len(pass1):.3f} ms, step (i) {sum(step_i) / len(step_i):.3f} ms, "
+          f"step (ii) {sum(step_ii) / len(step_ii):.3f} ms", file=sys.stderr, flush=True)
+
+    n_counts = 3 ** n * d
+    t_pass1 = sum(pass1) / len(pass1) / 1e3
+    achieved = 2.0 * n_counts / t_pass1 / 1e9
+    traffic = measured_traffic(args.workload)
+    algo_bytes = 2.0 * n_counts + 8.0 * 4 ** n + 16.0 * 4 ** n
+    out = {
+        "metric": METRIC,
+        "value": n_counts / (ms_step / 1e3),
+        "unit": "counts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32+f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "n": n, "shots": shots if shots else "per-basis",
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "fold_counts_kernel (counts pass of step (i))",
+                     "algorithmic_bytes_per_launch": 2.0 * n_counts},
+        "end_to_end_s": ms_step / 1e3,
+        "step_ms": {"counts_pass": t_pass1 * 1e3, "step_i": sum(step_i) / len(step_i),
+                    "step_ii": sum(step_ii) / len(step_ii)},
+        "whole_step_hbm_frac": algo_bytes / (ms_step / 1e3) / (HBM_PEAK_GBS * 1e9),
+        "mfma_vs_plain": None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.workload, n, shots, counts, coef)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,139 @@
+/*
+ * lre.h -- C ABI of the gfx950 (MI355X) library for linear regression estimation
+ * (LRE) of an n-qubit state from local Pauli measurement counts.
+ *
+ * Method: Hou et al., "Full reconstruction of a 14-qubit state within four hours"
+ * (arXiv:1602.08604).  The library implements the paper's steps (i) and (ii):
+ *   step (i)  Sec. II eq. (3) with the Pauli structure of Sec. III: the least-squares
+ *             coefficients Theta = (X^T X)^{-1} sum_j p_j Gamma^(j), where every
+ *             Gamma^(j) has 2^n nonzero entries and X^T X = (x)_k diag{3,1,1,1};
+ *   step (ii) Sec. II eq. (4): mu = sum_i theta_i Omega_i with Omega_i of eq. (5).
+ * Step (iii) (projection onto physical states) is not part of this library.
+ *
+ * Data layout (all device memory, row-major, caller-owned):
+ *   counts : uint16 [3^n][2^n].  Row b is one measurement setting,
+ *            b = sum_k b_k 3^{n-k} with b_k in {0:X, 1:Y, 2:Z} (qubit 1 most
+ *            significant); column s = sum_k s_k 2^{n-k}, s_k = 0 for the +1
+ *            eigenvector of the measured Pauli operator.  16-byte aligned.
+ *   coef   : double [4^n].  coef[i] = e_i = 2^{n/2} theta_i, the Pauli expectation
+ *            of the string with letters a_k (i = sum_k a_k 4^{n-k}, eq. 5;
+ *            a_k in {0:I, 1:X, 2:Y, 3:Z}).  coef[0] = 1 for every valid input.
+ *   rho    : [2^n][2^n] complex, interleaved (re, im), row r = sum_k r_k 2^{n-k}.
+ *            complex128 by default, complex64 with LRE_RHO_FP32.  16-byte aligned.
+ *            This is mu of eq. (4): Hermitian, unit trace, not necessarily positive.
+ * Frequencies p_j are taken within each basis, p = c[b][s] / N_b, N_b the basis total.
+ *
+ * Conventions common to every entry point:
+ *   - Calls enqueue work on `stream` (a hipStream_t; NULL = default stream) and return
+ *     without synchronising.  No entry point allocates device memory except
+ *     lre_create (a 64-byte flag word) and lre_batch_plan (its work list).
+ *   - Host-checkable problems (bad n, NULL or misaligned pointers, workspace too
+ *     small) return an error before anything is launched.
+ *   - Data-dependent problems are recorded in the context's device flag word and
+ *     reported by lre_check: a basis whose counts do not sum to the declared total
+ *     (LRE_E_SHOTS) or a basis with no counts in per-basis mode (LRE_E_EMPTY_BASIS).
+ *     Outputs are unspecified when a flag is raised.
+ *   - One lre_ctx per host thread, or external locking.  Calls that share a
+ *     workspace must be ordered on one stream.
+ *   - No C++ exception crosses this interface.
+ */
+#ifndef LRE_H
+#define LRE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LRE_OK = 0,
+  LRE_E_ARG = 1,          /* invalid argument (n out of range, NULL/misaligned pointer) */
+  LRE_E_WORKSPACE = 2,    /* workspace smaller than lre_workspace_bytes() */
+  LRE_E_HIP = 3,          /* a HIP runtime call failed */
+  LRE_E_SHOTS = 4,        /* a basis row does not sum to its declared total */
+  LRE_E_EMPTY_BASIS = 5,  /* per-basis mode: a basis with zero counts */
+  LRE_E_UNSUPPORTED = 6   /* valid request that this build cannot serve */
+} lre_status;
+
+#define LRE_MAX_QUBITS 14
+
+/* Flags (bitwise or). */
+#define LRE_NO_RHO 0x1u    /* skip step (ii); rho may be NULL */
+#define LRE_RHO_FP32 0x2u  /* write rho as complex64 instead of complex128 */
+#define LRE_WHT_MFMA 0x4u  /* signed outcome sums on int8 MFMA (bit-identical results) */
+
+typedef struct lre_ctx lre_ctx;
+
+/* Create a context on HIP device `hip_device`: allocates the 64-byte device flag
+ * word.  *out receives the context.  Errors: LRE_E_ARG (out == NULL), LRE_E_HIP. */
+lre_status lre_create(lre_ctx** out, int hip_device);
+
+/* Destroy a context created by lre_create (NULL is ignored). */
+void lre_destroy(lre_ctx* ctx);
+
+/* Static, human-readable name of a status code. */
+const char* lre_status_str(int status);
+
+/* Bytes of device workspace lre_estimate needs for this (n, shots, flags); 0 when n
+ * is out of range.  shots follows lre_estimate (0 = per-basis totals). */
+size_t lre_workspace_bytes(int n, uint64_t shots, uint32_t flags);
+
+/* Steps (i) and (ii) on one instance (Sec. II eqs. 3 and 4, Sec. III).
+ *   n           : 1 <= n <= LRE_MAX_QUBITS.
+ *   counts      : device uint16 [3^n][2^n], 16-byte aligned.
+ *   shots       : > 0  every basis totals exactly `shots` (checked); e_i is then the
+ *                      correctly rounded quotient of the exact integer sum
+ *                      T_i = sum_{b,s} c[b][s] 2^{n/2} gamma_i^(b,s) by 3^{n-w(i)} shots.
+ *                 == 0 per-basis totals N_b: taken from n_per_basis when non-NULL
+ *                      (checked against the row sums) or computed from the rows
+ *                      (one extra pass over counts); e_i = 3^{-(n-w)} sum_b S_b / N_b
+ *                      in binary64.
+ *   n_per_basis : device uint32 [3^n] or NULL; read only when shots == 0.
+ *   coef        : device double [4^n], written.
+ *   rho         : device complex [2^n][2^n] (see header), written unless LRE_NO_RHO.
+ *   workspace   : device memory of at least lre_workspace_bytes(n, shots, flags) bytes,
+ *                 256-byte aligned, caller-owned, contents need not be initialised.
+ *   flags       : LRE_NO_RHO | LRE_RHO_FP32 | LRE_WHT_MFMA.
+ *   stream      : hipStream_t to enqueue on.
+ * Returns LRE_OK once every kernel is enqueued. */
+lre_status lre_estimate(lre_ctx* ctx, int n, const uint16_t* counts, uint64_t shots,
+                        const uint32_t* n_per_basis, double* coef, void* rho, void* workspace,
+                        size_t workspace_bytes, uint32_t flags, void* stream);
+
+/* Synchronise `stream`, read and clear the context's device flag word.  Returns
+ * LRE_E_SHOTS, LRE_E_EMPTY_BASIS, LRE_E_HIP or LRE_OK. */
+lre_status lre_check(lre_ctx* ctx, void* stream);
+
+/* Profiling hook.  events: `count` (<= 4) caller-created hipEvent_t handles, or NULL to
+ * disable.  While set, lre_estimate records them on its stream at stage boundaries:
+ *   events[0] before its first kernel,        events[1] after the counts pass,
+ *   events[2] after the rest of step (i),     events[3] after step (ii).
+ * The caller owns the events and must keep them alive while they are set. */
+lre_status lre_set_stage_events(lre_ctx* ctx, void* const* events, int count);
+
+/* Exact integer numerators of eq. (3) with uniform shots (verification entry):
+ * T[i] = sum_{b,s} c[b][s] * prod_k g(a_k, b_k, s_k), g = 2^{1/2} gamma of the one-qubit
+ * projector (Sec. III), for every i < 4^n, as int64.  Same kernels as lre_estimate.
+ *   shots     : the declared per-basis total (checked; bounds the partial sums).
+ *   T         : device int64 [4^n].
+ *   workspace : at least lre_workspace_bytes(n, shots, flags | LRE_NO_RHO) bytes. */
+lre_status lre_pauli_sums(lre_ctx* ctx, int n, const uint16_t* counts, uint64_t shots,
+                          int64_t* T, void* workspace, size_t workspace_bytes, uint32_t flags,
+                          void* stream);
+
+/* Signed outcome sums of selected bases (verification entry):
+ * out[j][m] = sum_s c[b_j][s] (-1)^{popcount(s & m)} for m < 2^n, i.e. the per-basis
+ * part sum_s c gamma^(b,s)_i of eq. (3) at the coefficient i whose support is m.
+ *   bases : device int64 [num_bases], each in [0, 3^n) (an out-of-range entry yields
+ *           an all-zero row and raises LRE_E_ARG through lre_check).
+ *   out   : device int32 [num_bases][2^n]. */
+lre_status lre_signed_sums(lre_ctx* ctx, int n, const uint16_t* counts, const int64_t* bases,
+                           int64_t num_bases, int32_t* out, uint32_t flags, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LRE_H */

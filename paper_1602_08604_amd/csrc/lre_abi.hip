@@ -1,0 +1,461 @@
+// lre_abi.hip -- the C ABI declared in include/lre.h: argument checks, pass planning,
+// workspace layout and kernel launches.  All arithmetic runs in lre_kernels.hpp.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstdint>
+#include <cstring>
+
+#include "lre.h"
+#include "lre_kernels.hpp"
+
+using namespace lre;
+
+struct lre_ctx {
+  int device;
+  uint32_t* flags;              // device word: FLAG_* bits raised by the kernels
+  hipEvent_t stage_events[4];   // optional profiling events (lre_set_stage_events)
+  int n_stage_events;
+};
+
+namespace {
+void record_stage(lre_ctx* ctx, int k, hipStream_t st) {
+  if (k < ctx->n_stage_events && ctx->stage_events[k]) (void)hipEventRecord(ctx->stage_events[k], st);
+}
+}  // namespace
+
+namespace {
+
+constexpr int kMaxQ1 = 7;     // qubits folded by the counts pass
+constexpr int kMaxF = 3;      // qubits folded by a later pass
+constexpr int kMaxFLast = 2;  // qubits folded by the final pass
+constexpr int kRhoJ = 6;      // qubits of the low step-(ii) transform
+constexpr int kRhoXB = 8;     // row entries per block in the high step-(ii) transform
+constexpr int kRhoHMax = LRE_MAX_QUBITS - kRhoJ;
+
+enum class Ty : int { U32 = 0, F64 = 1 };
+
+size_t ty_size(Ty t) { return t == Ty::U32 ? 4 : 8; }
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+struct Plan {
+  int n = 0;
+  bool per_basis = false;
+  int q1 = 0;
+  int chunks = 1;            // tiles per counts-pass block
+  int64_t blocks1 = 0;       // counts-pass blocks
+  Ty t1 = Ty::U32;           // counts-pass accumulator / output type
+  int npass = 0;             // later passes
+  int F[8] = {0};
+  Ty tout[8] = {Ty::U32};
+  int J = 0;                 // low step-(ii) qubits
+  size_t off_a = 0, off_b = 0, off_rowpart = 0, off_nb = 0, off_tmp = 0, total = 0;
+};
+
+// Partial sums after folding f qubits are bounded by 3^f * (basis total).
+Ty int_type_for(int folded, uint64_t shots) {
+  long double bound = (long double)shots;
+  for (int i = 0; i < folded; ++i) bound *= 3.0L;
+  return bound <= (long double)INT32_MAX ? Ty::U32 : Ty::F64;
+}
+
+bool make_plan(int n, uint64_t shots, uint32_t flags, Plan& P) {
+  if (n < 1 || n > LRE_MAX_QUBITS) return false;
+  P = Plan();
+  P.n = n;
+  P.per_basis = shots == 0;
+  P.q1 = n < kMaxQ1 ? n : kMaxQ1;
+  const int64_t tiles_per_row = (int64_t)1 << (n - P.q1);
+  const int64_t row_groups = ipow3(n - P.q1);
+  int64_t chunks = 1;
+  while (chunks * 2 <= tiles_per_row && chunks < 16 &&
+         row_groups * (tiles_per_row / (chunks * 2)) >= 1024)
+    chunks *= 2;
+  P.chunks = (int)chunks;
+  P.blocks1 = row_groups * (tiles_per_row / chunks);
+  P.t1 = P.per_basis ? Ty::F64 : int_type_for(P.q1, shots);
+
+  // Later passes: the last folds at most kMaxFLast qubits (it also divides every
+  // output, which costs registers); the others split the rest evenly, <= kMaxF each.
+  const int h = n - P.q1;
+  const int last = h < kMaxFLast ? h : kMaxFLast;
+  const int rest = h - last;
+  const int nrest = (rest + kMaxF - 1) / kMaxF;
+  P.npass = nrest + (last > 0 ? 1 : 0);
+  for (int k = 0; k < nrest; ++k) P.F[k] = rest / nrest + (k < rest % nrest ? 1 : 0);
+  if (last > 0) P.F[nrest] = last;
+  int folded = P.q1;
+  Ty prev = P.t1;
+  for (int k = 0; k < P.npass; ++k) {
+    folded += P.F[k];
+    Ty t = P.per_basis ? Ty::F64 : int_type_for(folded, shots);
+    if (prev == Ty::F64) t = Ty::F64;
+    P.tout[k] = t;
+    prev = t;
+  }
+
+  // Workspace: ping-pong partial buffers A (counts pass, odd later passes) and B.
+  size_t sizeA = 0, sizeB = 0;
+  {
+    int hh = n - P.q1, ll = P.q1;
+    if (P.npass > 0) sizeA = (size_t)(ipow3(hh) << hh) * (size_t)ipow4(ll) * ty_size(P.t1);
+    for (int k = 0; k + 1 < P.npass; ++k) {  // outputs of all but the last later pass
+      hh -= P.F[k];
+      ll += P.F[k];
+      size_t sz = (size_t)(ipow3(hh) << hh) * (size_t)ipow4(ll) * ty_size(P.tout[k]);
+      if (k % 2 == 0) sizeB = sizeB > sz ? sizeB : sz;
+      else sizeA = sizeA > sz ? sizeA : sz;
+    }
+  }
+  const size_t rowpart = (size_t)P.blocks1 * (size_t)ipow3(P.q1) * 4;
+  const size_t nbytes = P.per_basis ? (size_t)ipow3(n) * 4 : 0;
+  P.J = n < kRhoJ ? n : kRhoJ;
+  const size_t tmp = (!(flags & LRE_NO_RHO) && n > P.J) ? (size_t)ipow4(n) * 16 : 0;
+
+  size_t off = 0;
+  P.off_a = off; off += align256(sizeA);
+  P.off_b = off; off += align256(sizeB);
+  P.off_rowpart = off; off += align256(rowpart);
+  P.off_nb = off; off += align256(nbytes);
+  if (tmp && tmp <= sizeA) P.off_tmp = P.off_a;        // partials are dead by then
+  else if (tmp && tmp <= sizeB) P.off_tmp = P.off_b;
+  else { P.off_tmp = off; off += align256(tmp); }
+  P.total = off;
+  return true;
+}
+
+// ---- launch helpers -------------------------------------------------------------
+
+struct Fold1Args {
+  const uint16_t* counts;
+  int n, chunks;
+  const uint32_t* nb;
+  void* out;
+  uint32_t* rowpart;
+  uint64_t shots;
+  int64_t blocks;
+  hipStream_t st;
+};
+
+constexpr int kRegDigits = 2;  // basis digits folded in registers by the counts pass
+
+template <int Q, typename Acc, bool PB, Out M>
+void launch_fold1(const Fold1Args& a) {
+  constexpr int TH = Q == 7 ? 512 : 256;
+  hipLaunchKernelGGL((fold_counts_kernel<Q, TH, kRegDigits, Acc, PB, M>), dim3((unsigned)a.blocks), dim3(TH), 0,
+                     a.st, a.counts, a.n, a.chunks, a.nb, a.out, a.rowpart, a.shots);
+}
+
+template <int Q>
+bool fold1_q(Ty t, bool pb, Out m, const Fold1Args& a) {
+  if (pb) {
+    if (m == Out::Partial) launch_fold1<Q, double, true, Out::Partial>(a);
+    else if (m == Out::CoefPerBasis) launch_fold1<Q, double, true, Out::CoefPerBasis>(a);
+    else return false;
+    return true;
+  }
+  if (t == Ty::U32) {
+    switch (m) {
+      case Out::Partial: launch_fold1<Q, uint32_t, false, Out::Partial>(a); return true;
+      case Out::CoefUniform: launch_fold1<Q, uint32_t, false, Out::CoefUniform>(a); return true;
+      case Out::PauliT: launch_fold1<Q, uint32_t, false, Out::PauliT>(a); return true;
+      default: return false;
+    }
+  }
+  switch (m) {
+    case Out::Partial: launch_fold1<Q, double, false, Out::Partial>(a); return true;
+    case Out::CoefUniform: launch_fold1<Q, double, false, Out::CoefUniform>(a); return true;
+    case Out::PauliT: launch_fold1<Q, double, false, Out::PauliT>(a); return true;
+    default: return false;
+  }
+}
+
+bool fold1(int q, Ty t, bool pb, Out m, const Fold1Args& a) {
+  switch (q) {
+    case 1: return fold1_q<1>(t, pb, m, a);
+    case 2: return fold1_q<2>(t, pb, m, a);
+    case 3: return fold1_q<3>(t, pb, m, a);
+    case 4: return fold1_q<4>(t, pb, m, a);
+    case 5: return fold1_q<5>(t, pb, m, a);
+    case 6: return fold1_q<6>(t, pb, m, a);
+    case 7: return fold1_q<7>(t, pb, m, a);
+    default: return false;
+  }
+}
+
+struct FoldKArgs {
+  const void* in;
+  void* out;
+  int n, h, l;
+  uint64_t shots;
+  int64_t ncols;
+  hipStream_t st;
+};
+
+template <int F, typename Tin, typename Acc, Out M>
+void launch_foldk(const FoldKArgs& a) {
+  const int64_t blocks = (a.ncols + 255) / 256;
+  hipLaunchKernelGGL((fold_partial_kernel<F, Tin, Acc, M>), dim3((unsigned)blocks), dim3(256), 0, a.st,
+                     static_cast<const Tin*>(a.in), a.out, a.n, a.h, a.l, a.shots, a.ncols);
+}
+
+template <int F, typename Tin, typename Acc>
+bool foldk_m(Out m, const FoldKArgs& a) {
+  switch (m) {
+    case Out::Partial: launch_foldk<F, Tin, Acc, Out::Partial>(a); return true;
+    case Out::CoefUniform: launch_foldk<F, Tin, Acc, Out::CoefUniform>(a); return true;
+    case Out::CoefPerBasis: launch_foldk<F, Tin, Acc, Out::CoefPerBasis>(a); return true;
+    case Out::PauliT: launch_foldk<F, Tin, Acc, Out::PauliT>(a); return true;
+  }
+  return false;
+}
+
+template <int F>
+bool foldk_f(Ty tin, Ty tacc, Out m, const FoldKArgs& a) {
+  if (tin == Ty::U32 && tacc == Ty::U32) return foldk_m<F, uint32_t, uint32_t>(m, a);
+  if (tin == Ty::U32 && tacc == Ty::F64) return foldk_m<F, uint32_t, double>(m, a);
+  if (tin == Ty::F64 && tacc == Ty::F64) return foldk_m<F, double, double>(m, a);
+  return false;
+}
+
+bool foldk(int F, Ty tin, Ty tacc, Out m, const FoldKArgs& a) {
+  switch (F) {
+    case 1: return foldk_f<1>(tin, tacc, m, a);
+    case 2: return foldk_f<2>(tin, tacc, m, a);
+    case 3: return foldk_f<3>(tin, tacc, m, a);
+    default: return false;
+  }
+}
+
+template <typename OutT>
+void launch_rho(const Plan& P, const double* coef, void* rho, char* ws, hipStream_t st) {
+  const int n = P.n;
+  if (n <= kRhoJ) {
+    switch (n) {
+#define LRE_RHO_SMALL(J) \
+  case J: hipLaunchKernelGGL((rho_low_kernel<J, true, OutT>), dim3(1), dim3(256), 0, st, coef, rho, n); break;
+      LRE_RHO_SMALL(1) LRE_RHO_SMALL(2) LRE_RHO_SMALL(3) LRE_RHO_SMALL(4) LRE_RHO_SMALL(5) LRE_RHO_SMALL(6)
+#undef LRE_RHO_SMALL
+    }
+    return;
+  }
+  double2* tmp = reinterpret_cast<double2*>(ws + P.off_tmp);
+  hipLaunchKernelGGL((rho_low_kernel<kRhoJ, false, OutT>), dim3((unsigned)ipow4(n - kRhoJ)), dim3(256), 0, st,
+                     coef, (void*)tmp, n);
+  const int64_t D = (int64_t)1 << kRhoJ;
+  const int64_t blocks = ((int64_t)1 << (n - kRhoJ)) * D * (D / kRhoXB);
+  hipLaunchKernelGGL((rho_high_kernel<kRhoXB, kRhoHMax, OutT>), dim3((unsigned)blocks), dim3(256), 0, st,
+                     (const double2*)tmp, rho, n, (int)kRhoJ);
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) { ok = false; return; }
+    if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+// Step (i) into `final_out` (coef or T) with final mode `fm`.
+lre_status run_step1(lre_ctx* ctx, const Plan& P, const uint16_t* counts, uint64_t shots,
+                     const uint32_t* nb_in, void* final_out, Out fm, char* ws, hipStream_t st) {
+  const int n = P.n;
+  const int64_t nbases = ipow3(n);
+  const uint32_t* nb = nb_in;
+  if (P.per_basis && !nb) {
+    uint32_t* nbd = reinterpret_cast<uint32_t*>(ws + P.off_nb);
+    hipLaunchKernelGGL(row_totals_kernel, dim3((unsigned)nbases), dim3(256), 0, st, counts, n, nbd);
+    nb = nbd;
+  }
+  uint32_t* rowpart = reinterpret_cast<uint32_t*>(ws + P.off_rowpart);
+
+  Fold1Args a1{counts, n, P.chunks, nb, nullptr, rowpart, shots, P.blocks1, st};
+  const bool single = P.npass == 0;
+  a1.out = single ? final_out : (void*)(ws + P.off_a);
+  if (!fold1(P.q1, P.t1, P.per_basis, single ? fm : Out::Partial, a1)) return LRE_E_UNSUPPORTED;
+  if (hipGetLastError() != hipSuccess) return LRE_E_HIP;
+  record_stage(ctx, 1, st);
+
+  int h = n - P.q1, l = P.q1;
+  Ty tin = P.t1;
+  for (int k = 0; k < P.npass; ++k) {
+    const bool last = k + 1 == P.npass;
+    FoldKArgs ak;
+    ak.in = ws + (k % 2 == 0 ? P.off_a : P.off_b);
+    ak.out = last ? final_out : (void*)(ws + (k % 2 == 0 ? P.off_b : P.off_a));
+    ak.n = n;
+    ak.h = h;
+    ak.l = l;
+    ak.shots = shots;
+    ak.ncols = (ipow3(h - P.F[k]) << (h - P.F[k])) * ipow4(l);
+    ak.st = st;
+    if (!foldk(P.F[k], tin, P.tout[k], last ? fm : Out::Partial, ak)) return LRE_E_UNSUPPORTED;
+    if (hipGetLastError() != hipSuccess) return LRE_E_HIP;
+    h -= P.F[k];
+    l += P.F[k];
+    tin = P.tout[k];
+  }
+
+  const int64_t rows = ipow3(P.q1);
+  const int64_t runs = ((int64_t)1 << (n - P.q1)) / P.chunks;
+  hipLaunchKernelGGL(check_rows_kernel, dim3((unsigned)((nbases + 255) / 256)), dim3(256), 0, st,
+                     (const uint32_t*)rowpart, rows, runs, nb, P.per_basis ? (uint64_t)0 : shots, nbases,
+                     ctx->flags);
+  return hipGetLastError() == hipSuccess ? LRE_OK : LRE_E_HIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lre_status_str(int s) {
+  switch (s) {
+    case LRE_OK: return "ok";
+    case LRE_E_ARG: return "invalid argument";
+    case LRE_E_WORKSPACE: return "workspace too small";
+    case LRE_E_HIP: return "HIP runtime error";
+    case LRE_E_SHOTS: return "a basis row does not sum to its declared total";
+    case LRE_E_EMPTY_BASIS: return "a basis has zero counts";
+    case LRE_E_UNSUPPORTED: return "unsupported request";
+    default: return "unknown status";
+  }
+}
+
+lre_status lre_create(lre_ctx** out, int hip_device) {
+  if (!out) return LRE_E_ARG;
+  *out = nullptr;
+  DeviceGuard g(hip_device);
+  if (!g.ok) return LRE_E_HIP;
+  lre_ctx* c = new (std::nothrow) lre_ctx;
+  if (!c) return LRE_E_HIP;
+  c->device = hip_device;
+  c->flags = nullptr;
+  c->n_stage_events = 0;
+  for (auto& e : c->stage_events) e = nullptr;
+  if (hipMalloc(&c->flags, 64) != hipSuccess) { delete c; return LRE_E_HIP; }
+  if (hipMemset(c->flags, 0, 64) != hipSuccess) { (void)hipFree(c->flags); delete c; return LRE_E_HIP; }
+  *out = c;
+  return LRE_OK;
+}
+
+void lre_destroy(lre_ctx* ctx) {
+  if (!ctx) return;
+  DeviceGuard g(ctx->device);
+  (void)hipFree(ctx->flags);
+  delete ctx;
+}
+
+size_t lre_workspace_bytes(int n, uint64_t shots, uint32_t flags) {
+  Plan P;
+  if (!make_plan(n, shots, flags, P)) return 0;
+  return P.total;
+}
+
+lre_status lre_estimate(lre_ctx* ctx, int n, const uint16_t* counts, uint64_t shots,
+                        const uint32_t* n_per_basis, double* coef, void* rho, void* workspace,
+                        size_t workspace_bytes, uint32_t flags, void* stream) {
+  if (!ctx || !counts || !coef || n < 1 || n > LRE_MAX_QUBITS) return LRE_E_ARG;
+  if (flags & ~(LRE_NO_RHO | LRE_RHO_FP32 | LRE_WHT_MFMA)) return LRE_E_ARG;
+  if (!aligned(counts, 16) || !aligned(coef, 8)) return LRE_E_ARG;
+  const bool want_rho = !(flags & LRE_NO_RHO);
+  if (want_rho && (!rho || !aligned(rho, 16))) return LRE_E_ARG;
+  if (flags & LRE_WHT_MFMA) return LRE_E_UNSUPPORTED;
+  Plan P;
+  if (!make_plan(n, shots, flags, P)) return LRE_E_ARG;
+  if (P.total && (!workspace || !aligned(workspace, 256))) return LRE_E_ARG;
+  if (workspace_bytes < P.total) return LRE_E_WORKSPACE;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return LRE_E_HIP;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+
+  record_stage(ctx, 0, st);
+  lre_status s = run_step1(ctx, P, counts, shots, n_per_basis, coef,
+                           P.per_basis ? Out::CoefPerBasis : Out::CoefUniform, ws, st);
+  if (s != LRE_OK) return s;
+  record_stage(ctx, 2, st);
+  if (want_rho) {
+    if (flags & LRE_RHO_FP32) launch_rho<float>(P, coef, rho, ws, st);
+    else launch_rho<double>(P, coef, rho, ws, st);
+    if (hipGetLastError() != hipSuccess) return LRE_E_HIP;
+  }
+  record_stage(ctx, 3, st);
+  return LRE_OK;
+}
+
+lre_status lre_set_stage_events(lre_ctx* ctx, void* const* events, int count) {
+  if (!ctx || count < 0 || count > 4 || (count > 0 && !events)) return LRE_E_ARG;
+  ctx->n_stage_events = events ? count : 0;
+  for (int k = 0; k < 4; ++k)
+    ctx->stage_events[k] = (events && k < count) ? static_cast<hipEvent_t>(events[k]) : nullptr;
+  return LRE_OK;
+}
+
+lre_status lre_check(lre_ctx* ctx, void* stream) {
+  if (!ctx) return LRE_E_ARG;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return LRE_E_HIP;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (hipStreamSynchronize(st) != hipSuccess) return LRE_E_HIP;
+  uint32_t f = 0;
+  if (hipMemcpy(&f, ctx->flags, sizeof f, hipMemcpyDeviceToHost) != hipSuccess) return LRE_E_HIP;
+  if (f) {
+    const uint32_t zero = 0;
+    if (hipMemcpy(ctx->flags, &zero, sizeof zero, hipMemcpyHostToDevice) != hipSuccess) return LRE_E_HIP;
+  }
+  if (f & FLAG_ARG) return LRE_E_ARG;
+  if (f & FLAG_EMPTY) return LRE_E_EMPTY_BASIS;
+  if (f & FLAG_SHOTS) return LRE_E_SHOTS;
+  return LRE_OK;
+}
+
+lre_status lre_pauli_sums(lre_ctx* ctx, int n, const uint16_t* counts, uint64_t shots, int64_t* T,
+                          void* workspace, size_t workspace_bytes, uint32_t flags, void* stream) {
+  if (!ctx || !counts || !T || n < 1 || n > LRE_MAX_QUBITS || shots == 0) return LRE_E_ARG;
+  if (flags & ~(LRE_NO_RHO | LRE_RHO_FP32 | LRE_WHT_MFMA)) return LRE_E_ARG;
+  if (!aligned(counts, 16) || !aligned(T, 8)) return LRE_E_ARG;
+  if (flags & LRE_WHT_MFMA) return LRE_E_UNSUPPORTED;
+  Plan P;
+  if (!make_plan(n, shots, flags | LRE_NO_RHO, P)) return LRE_E_ARG;
+  if (P.total && (!workspace || !aligned(workspace, 256))) return LRE_E_ARG;
+  if (workspace_bytes < P.total) return LRE_E_WORKSPACE;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return LRE_E_HIP;
+  return run_step1(ctx, P, counts, shots, nullptr, T, Out::PauliT, static_cast<char*>(workspace),
+                   static_cast<hipStream_t>(stream));
+}
+
+lre_status lre_signed_sums(lre_ctx* ctx, int n, const uint16_t* counts, const int64_t* bases,
+                           int64_t num_bases, int32_t* out, uint32_t flags, void* stream) {
+  if (!ctx || !counts || !bases || !out || n < 1 || n > LRE_MAX_QUBITS || num_bases < 0)
+    return LRE_E_ARG;
+  if (flags & ~(LRE_WHT_MFMA)) return LRE_E_ARG;
+  if (flags & LRE_WHT_MFMA) return LRE_E_UNSUPPORTED;
+  if (!aligned(counts, 16) || !aligned(out, 4) || !aligned(bases, 8)) return LRE_E_ARG;
+  if (num_bases == 0) return LRE_OK;
+  if (num_bases > INT32_MAX) return LRE_E_ARG;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return LRE_E_HIP;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t lds = (size_t)4 << n;
+  const int q = n < kMaxQ1 ? n : kMaxQ1;
+  switch (q) {
+#define LRE_SS(Q)                                                                                  \
+  case Q:                                                                                          \
+    hipLaunchKernelGGL(signed_sums_kernel<Q>, dim3((unsigned)num_bases), dim3(256), lds, st, counts, n, \
+                       bases, out, ctx->flags);                                                    \
+    break;
+    LRE_SS(1) LRE_SS(2) LRE_SS(3) LRE_SS(4) LRE_SS(5) LRE_SS(6) LRE_SS(7)
+#undef LRE_SS
+  }
+  return hipGetLastError() == hipSuccess ? LRE_OK : LRE_E_HIP;
+}
+
+}  // extern "C"

@@ -1,0 +1,588 @@
+// lre_kernels.hpp -- gfx950 kernels for LRE steps (i) and (ii).
+//
+// Step (i) (Sec. II eq. 3 with the Pauli structure of Sec. III) is the tensor map
+//   T = ((x)_k B) c,  B = 4x6 integer matrix on one qubit's (basis letter, outcome bit),
+// whose rows are the one-qubit Gamma vectors (times sqrt 2) of Sec. III:
+//   a = I : +1 for every (letter, outcome)            (the Gamma_0 entries)
+//   a = X : +1 / -1 on (X, +) / (X, -), 0 elsewhere    (likewise Y, Z)
+// B factors as (sum-or-select over the 3 letters) . (2-point Hadamard on the outcome
+// bit), so a qubit is "folded" by a Walsh-Hadamard butterfly on its outcome bit
+// followed by: I <- sum over letters of the even part, X/Y/Z <- the odd part of the
+// matching letter.  Folding a group of qubits turns 6 values per qubit into 4.
+// (X^T X)^{-1} = (x)_k diag{1/3,1,1,1} is applied once at the end as a division by
+// 3^{n-w(i)} (w = number of non-identity letters).
+//
+// Tensor layout between passes (row-major, mixed radix):
+//   [b_hi : 3^h][s_hi : 2^h][a_lo : 4^l]
+// h qubits still raw (basis letter digits, outcome bits), l qubits folded into
+// Pauli letters.  Qubit positions count from the least significant (position p has
+// weight 3^p in b, 2^p in s, 4^p in the Pauli index), so the lowest qubits fold first.
+//
+// Pass 1 (fold_counts_kernel) streams the uint16 counts once and folds the lowest Q
+// qubits: a tile is 3^Q rows x 2^Q consecutive outcomes; each lane owns 8 outcomes of
+// 9 rows, does the butterflies in registers and across the LPC lanes of the tile
+// row, folds the 2 lowest qubits in registers and adds the result into a 4^Q LDS
+// accumulator.  Later passes (fold_partial_kernel) fold up to 3 more qubits per pass,
+// one thread per column of the fastest-varying a_lo index, entirely in registers.
+//
+// Step (ii) (Sec. II eq. 4): with x = r XOR c, the entry mu[r][r^x] is a Walsh-Hadamard
+// transform over z in {0,1}^n of e_{a(x,z)} (-i)^{|x&z|}, where per qubit the pair
+// (x_k, z_k) = (0,0),(1,0),(1,1),(0,1) is the letter I, X, Y, Z (the paper's grouping of
+// the Omega_i by nonzero pattern, Sec. IV).  rho_low_kernel transforms the low J
+// qubits of each 4^J block of coefficients; rho_high_kernel the remaining high qubits
+// and writes the row-major matrix.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+namespace lre {
+
+__host__ __device__ constexpr int64_t ipow3(int k) { return k <= 0 ? 1 : 3 * ipow3(k - 1); }
+__host__ __device__ constexpr int64_t ipow4(int k) { return k <= 0 ? 1 : 4 * ipow4(k - 1); }
+__host__ __device__ constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
+
+enum : uint32_t { FLAG_SHOTS = 1u, FLAG_EMPTY = 2u, FLAG_ARG = 4u };
+
+// What the final pass writes.
+enum class Out : int { Partial = 0, CoefUniform = 1, CoefPerBasis = 2, PauliT = 3 };
+
+// Number of non-identity letters of a Pauli index (base-4 digits).
+__device__ __forceinline__ int pauli_weight(uint64_t a) {
+  return __popcll((a | (a >> 1)) & 0x5555555555555555ull);
+}
+
+// 3^k as an exact binary64 (k <= 33).
+__device__ __forceinline__ double pow3d(int k) {
+  double r = 1.0;
+  for (int i = 0; i < k; ++i) r *= 3.0;
+  return r;
+}
+
+// Compile-time helpers for the register fold of RD basis digits.
+// Letter digit of position p in a small Pauli index ar, and base-3 digit of beta.
+__host__ __device__ constexpr int adig(int ar, int p) { return (ar >> (2 * p)) & 3; }
+__host__ __device__ constexpr int bdig(int beta, int p) { return p == 0 ? beta % 3 : bdig(beta / 3, p - 1); }
+// Walsh index bits selected by ar: bit p set iff letter p is not the identity.
+__host__ __device__ constexpr int mlo_of(int ar, int rd) {
+  return rd == 0 ? 0 : (mlo_of(ar, rd - 1) | ((adig(ar, rd - 1) != 0) << (rd - 1)));
+}
+// Does basis row beta contribute to Pauli letters ar on the rd lowest positions?
+__host__ __device__ constexpr bool compat(int beta, int ar, int rd) {
+  return rd == 0 ? true
+                 : (compat(beta, ar, rd - 1) &&
+                    (adig(ar, rd - 1) == 0 || adig(ar, rd - 1) == bdig(beta, rd - 1) + 1));
+}
+
+// Value of the Pauli index restricted to the positions of a folded block, for basis
+// digits beta (base 3) and Walsh index m (base 2) of F positions.
+__host__ __device__ constexpr int fold_index(int beta, int m, int f) {
+  return f == 0 ? 0
+                : (fold_index(beta, m, f - 1) |
+                   ((((m >> (f - 1)) & 1) ? (bdig(beta, f - 1) + 1) : 0) << (2 * (f - 1))));
+}
+
+// Compile-time loop: f(std::integral_constant<int, I>) for I in [B, E).
+template <int B, int E>
+struct StaticFor {
+  template <class Fn>
+  __device__ __forceinline__ static void run(Fn&& f) {
+    if constexpr (B < E) {
+      f(std::integral_constant<int, B>{});
+      StaticFor<B + 1, E>::run(f);
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------------
+// Walsh-Hadamard butterflies.  Natural order: after the transform element m holds
+// sum_s x_s (-1)^{popcount(s & m)}.
+
+template <int NB, typename T>
+__device__ __forceinline__ void wht_regs(T* x) {
+#pragma unroll
+  for (int bit = 0; bit < NB; ++bit) {
+#pragma unroll
+    for (int v = 0; v < (1 << NB); ++v) {
+      if (v & (1 << bit)) continue;
+      T a = x[v], b = x[v | (1 << bit)];
+      x[v] = a + b;
+      x[v | (1 << bit)] = a - b;
+    }
+  }
+}
+
+// Butterflies across the low NL bits of the lane index (partners within a group of
+// 2^NL consecutive lanes).  The lower lane keeps x + partner, the upper partner - x.
+template <int NL, int V>
+__device__ __forceinline__ void wht_lanes(int32_t* x, int lam) {
+#pragma unroll
+  for (int bit = 0; bit < NL; ++bit) {
+    const bool upper = (lam >> bit) & 1;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      int32_t p = __shfl_xor(x[v], 1 << bit, 64);
+      x[v] = upper ? (p - x[v]) : (x[v] + p);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// Pass 1: counts -> partials (or the final coefficients when Q == n).
+
+template <int Q, int RDMAX = 2>
+struct Fold1Geom {
+  static constexpr int V = Q >= 3 ? 8 : (1 << Q);  // outcomes per lane
+  static constexpr int LB = ilog2c(V);              // Walsh bits held in registers
+  static constexpr int LPC = (1 << Q) / V;          // lanes per tile row
+  static constexpr int LL = Q - LB;                 // Walsh bits across lanes
+  static constexpr int RD = LB >= RDMAX ? RDMAX : LB;  // basis digits folded in registers
+  static constexpr int R = (int)ipow3(RD);          // rows per lane
+  static constexpr int NAR = (int)ipow4(RD);        // register-folded letters
+  static constexpr int VH = V >> RD;                // Walsh values per lane per letter
+  static constexpr int RS = (int)ipow3(Q - RD);     // row-sets per tile
+  static constexpr int NACC = (int)ipow4(Q);        // accumulators per tile
+  static constexpr int NROWS = (int)ipow3(Q);       // rows per tile
+};
+
+template <int V>
+__device__ __forceinline__ void load_counts(const uint16_t* __restrict__ p, int32_t* x) {
+  if constexpr (V == 8) {
+    uint4 w = *reinterpret_cast<const uint4*>(p);
+    uint32_t u[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) { x[2 * k] = (int32_t)(u[k] & 0xffffu); x[2 * k + 1] = (int32_t)(u[k] >> 16); }
+  } else if constexpr (V == 4) {
+    uint2 w = *reinterpret_cast<const uint2*>(p);
+    x[0] = (int32_t)(w.x & 0xffffu); x[1] = (int32_t)(w.x >> 16);
+    x[2] = (int32_t)(w.y & 0xffffu); x[3] = (int32_t)(w.y >> 16);
+  } else {
+    uint32_t w = *reinterpret_cast<const uint32_t*>(p);
+    x[0] = (int32_t)(w & 0xffffu); x[1] = (int32_t)(w >> 16);
+  }
+}
+
+// Accumulator conversion of an exact chunk sum.
+template <typename Acc>
+__device__ __forceinline__ Acc to_acc(int32_t s) {
+  if constexpr (sizeof(Acc) == 4) return (Acc)(uint32_t)s;  // wrap-around integer
+  else return (Acc)s;
+}
+
+template <typename Acc>
+__device__ __forceinline__ double acc_to_double(Acc v) {
+  if constexpr (sizeof(Acc) == 4) return (double)(int32_t)(uint32_t)v;
+  else return (double)v;
+}
+
+template <typename Acc>
+__device__ __forceinline__ int64_t acc_to_i64(Acc v) {
+  if constexpr (sizeof(Acc) == 4) return (int64_t)(int32_t)(uint32_t)v;
+  else return (int64_t)v;
+}
+
+// counts : [3^n][2^n] uint16.  Block -> (b_hi, run of `chunks` consecutive s_hi).
+// out    : Partial: Acc [3^{n-Q}][2^{n-Q}][4^Q]; CoefUniform / CoefPerBasis: double
+//          [4^n]; PauliT: int64 [4^n]  (the final modes require Q == n).
+// rowpart: uint32 [3^{n-Q}][runs][3^Q]: the block's partial row sums (runs = blocks
+//          per row group); check_rows_kernel adds the runs and checks the totals.
+// nb     : per-basis totals (PER_BASIS only).
+template <int Q, int THREADS, int RDMAX, typename Acc, bool PER_BASIS, Out MODE>
+__global__ __launch_bounds__(THREADS) void fold_counts_kernel(
+    const uint16_t* __restrict__ counts, int n, int chunks, const uint32_t* __restrict__ nb,
+    void* __restrict__ out, uint32_t* __restrict__ rowpart, uint64_t shots) {
+  using G = Fold1Geom<Q, RDMAX>;
+  constexpr int GROUPS = THREADS / G::LPC;
+  __shared__ Acc acc[G::NACC];
+  __shared__ uint32_t rs_acc[G::NROWS];
+
+  const int tid = threadIdx.x;
+  const int grp = tid / G::LPC, lam = tid % G::LPC;
+  const int64_t n_shi = (int64_t)1 << (n - Q);
+  const int64_t runs_per_row = n_shi / chunks;
+  const int64_t b_hi = blockIdx.x / runs_per_row;
+  const int64_t s_hi0 = (blockIdx.x % runs_per_row) * chunks;
+  const int64_t row0 = b_hi * G::NROWS;
+  const int64_t rowlen = (int64_t)1 << n;
+
+  for (int i = tid; i < G::NACC; i += THREADS) acc[i] = Acc(0);
+  for (int i = tid; i < G::NROWS; i += THREADS) rs_acc[i] = 0;
+  __syncthreads();
+
+  for (int c = 0; c < chunks; ++c) {
+    const int64_t s_hi = s_hi0 + c;
+    for (int rs = grp; rs < G::RS; rs += GROUPS) {
+      const int64_t rowb = row0 + (int64_t)rs * G::R;
+      int32_t x[G::R][G::V];
+#pragma unroll
+      for (int beta = 0; beta < G::R; ++beta)
+        load_counts<G::V>(counts + (rowb + beta) * rowlen + (s_hi << Q) + lam * G::V, x[beta]);
+
+#pragma unroll
+      for (int beta = 0; beta < G::R; ++beta) {
+        wht_regs<G::LB>(x[beta]);
+        wht_lanes<G::LL, G::V>(x[beta], lam);
+      }
+      if (lam == 0) {
+#pragma unroll
+        for (int beta = 0; beta < G::R; ++beta) atomicAdd(&rs_acc[rs * G::R + beta], (uint32_t)x[beta][0]);
+      }
+
+      // Fold the RD lowest qubits in registers: o[vh][ar] sums, over the rows beta of
+      // the row-set compatible with letters ar, the Walsh value whose low RD bits
+      // select the non-identity letters.  Per-basis mode divides each row by N_b first.
+      Acc o[G::VH][G::NAR];
+#pragma unroll
+      for (int vh = 0; vh < G::VH; ++vh)
+#pragma unroll
+        for (int ar = 0; ar < G::NAR; ++ar) o[vh][ar] = Acc(0);
+      StaticFor<0, G::R>::run([&](auto bc) __attribute__((always_inline)) {
+        constexpr int beta = decltype(bc)::value;
+        Acc y[G::V];
+        if constexpr (PER_BASIS) {
+          const uint32_t N = nb[rowb + beta];
+          const double keep = N ? 1.0 : 0.0;  // empty basis: flagged by the row check
+          const double Nd = N ? (double)N : 1.0;
+#pragma unroll
+          for (int v = 0; v < G::V; ++v) y[v] = keep * ((double)x[beta][v] / Nd);
+        } else {
+#pragma unroll
+          for (int v = 0; v < G::V; ++v) y[v] = to_acc<Acc>(x[beta][v]);
+        }
+        StaticFor<0, G::NAR>::run([&](auto ac) __attribute__((always_inline)) {
+          constexpr int ar = decltype(ac)::value;
+          if constexpr (compat(beta, ar, G::RD)) {
+            constexpr int ml = mlo_of(ar, G::RD);
+#pragma unroll
+            for (int vh = 0; vh < G::VH; ++vh) o[vh][ar] += y[(vh << G::RD) | ml];
+          }
+        });
+      });
+
+      // Accumulator address: letters of the positions above RD come from the Walsh
+      // bits (register bits RD..LB-1, lane bits) and the basis digits of the row-set.
+      uint32_t base = 0;
+      uint32_t tv[G::LB - G::RD > 0 ? G::LB - G::RD : 1] = {};
+      {
+        int t = rs;
+        StaticFor<0, Q - G::RD>::run([&](auto jc) __attribute__((always_inline)) {
+          constexpr int j = decltype(jc)::value;
+          constexpr int p = G::RD + j;
+          const uint32_t term = (uint32_t)(t % 3 + 1) << (2 * p);
+          t /= 3;
+          if constexpr (p < G::LB) tv[j] = term;
+          else if ((lam >> (p - G::LB)) & 1) base += term;
+        });
+      }
+#pragma unroll
+      for (int vh = 0; vh < G::VH; ++vh) {
+        uint32_t off = base;
+#pragma unroll
+        for (int q = 0; q < G::LB - G::RD; ++q)
+          if ((vh >> q) & 1) off += tv[q];
+#pragma unroll
+        for (int ar = 0; ar < G::NAR; ++ar) atomicAdd(&acc[off + ar], o[vh][ar]);
+      }
+    }
+    __syncthreads();
+
+    for (int i = tid; i < G::NACC; i += THREADS) {
+      const Acc v = acc[i];
+      acc[i] = Acc(0);
+      if constexpr (MODE == Out::Partial) {
+        static_cast<Acc*>(out)[(b_hi * n_shi + s_hi) * G::NACC + i] = v;
+      } else if constexpr (MODE == Out::CoefUniform) {
+        const int w = pauli_weight((uint64_t)i);
+        static_cast<double*>(out)[i] = acc_to_double(v) / (pow3d(n - w) * (double)shots);
+      } else if constexpr (MODE == Out::CoefPerBasis) {
+        const int w = pauli_weight((uint64_t)i);
+        static_cast<double*>(out)[i] = acc_to_double(v) / pow3d(n - w);
+      } else {
+        static_cast<int64_t*>(out)[i] = acc_to_i64(v);
+      }
+    }
+    __syncthreads();
+  }
+
+  uint32_t* __restrict__ rp = rowpart + (int64_t)blockIdx.x * G::NROWS;
+  for (int i = tid; i < G::NROWS; i += THREADS) rp[i] = rs_acc[i];
+}
+
+// ---------------------------------------------------------------------------------
+// Later passes: [3^h][2^h][4^l] -> [3^{h-F}][2^{h-F}][4^{F+l}], one thread per column
+// (b_hi, s_hi, a_lo), a_lo fastest so that loads and stores are coalesced.
+
+template <typename Tin, typename Acc>
+__device__ __forceinline__ Acc in_to_acc(Tin v) {
+  if constexpr (sizeof(Tin) == 4 && sizeof(Acc) == 4) return (Acc)(uint32_t)v;
+  else if constexpr (sizeof(Tin) == 4) return (Acc)(int32_t)(uint32_t)v;
+  else return (Acc)v;
+}
+
+template <int F, typename Tin, typename Acc, Out MODE>
+__global__ __launch_bounds__(256) void fold_partial_kernel(const Tin* __restrict__ in,
+                                                           void* __restrict__ out, int n, int h,
+                                                           int l, uint64_t shots, int64_t ncols) {
+  const int64_t col = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (col >= ncols) return;
+  const int64_t L = (int64_t)1 << (2 * l);
+  const int64_t a_l = col & (L - 1);
+  const int64_t bs = col >> (2 * l);
+  const int hr = h - F;
+  const int64_t s_hi = bs & (((int64_t)1 << hr) - 1);
+  const int64_t b_hi = bs >> hr;
+  const int64_t rowstride = ((int64_t)1 << h) * L;
+  const Tin* __restrict__ p0 = in + b_hi * ipow3(F) * rowstride + (s_hi << F) * L + a_l;
+
+  constexpr int NA = (int)ipow4(F);
+  Acc acc[NA];
+  StaticFor<0, NA>::run([&](auto ac) __attribute__((always_inline)) { acc[decltype(ac)::value] = Acc(0); });
+  StaticFor<0, (int)ipow3(F)>::run([&](auto bc) __attribute__((always_inline)) {
+    constexpr int beta = decltype(bc)::value;
+    Acc x[1 << F];
+#pragma unroll
+    for (int sg = 0; sg < (1 << F); ++sg) x[sg] = in_to_acc<Tin, Acc>(p0[beta * rowstride + sg * L]);
+    wht_regs<F>(x);
+    StaticFor<0, (1 << F)>::run([&](auto mc) __attribute__((always_inline)) {
+      constexpr int m = decltype(mc)::value;
+      constexpr int a = fold_index(beta, m, F);
+      acc[a] += x[m];
+    });
+  });
+
+  if constexpr (MODE == Out::Partial) {
+    Acc* o = static_cast<Acc*>(out) + bs * (NA * L) + a_l;
+    StaticFor<0, NA>::run([&](auto ac) __attribute__((always_inline)) {
+      constexpr int a = decltype(ac)::value;
+      o[a * L] = acc[a];
+    });
+  } else {
+    const int wl = pauli_weight((uint64_t)a_l);
+    StaticFor<0, NA>::run([&](auto ac) __attribute__((always_inline)) {
+      constexpr int a = decltype(ac)::value;
+      const int64_t i = a * L + a_l;
+      const int w = wl + __builtin_popcount((a | (a >> 1)) & 0x55555555);
+      if constexpr (MODE == Out::CoefUniform)
+        static_cast<double*>(out)[i] = acc_to_double(acc[a]) / (pow3d(n - w) * (double)shots);
+      else if constexpr (MODE == Out::CoefPerBasis)
+        static_cast<double*>(out)[i] = acc_to_double(acc[a]) / pow3d(n - w);
+      else
+        static_cast<int64_t*>(out)[i] = acc_to_i64(acc[a]);
+    });
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// Row totals: zero fill, per-basis totals (when not supplied), and the final check.
+
+__global__ void fill_u32_kernel(uint32_t* __restrict__ p, int64_t count, uint32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < count) p[i] = v;
+}
+
+// One block of 256 threads per basis row.
+__global__ __launch_bounds__(256) void row_totals_kernel(const uint16_t* __restrict__ counts,
+                                                         int n, uint32_t* __restrict__ nb) {
+  const int64_t b = blockIdx.x;
+  const int64_t d = (int64_t)1 << n;
+  const uint16_t* row = counts + b * d;
+  uint32_t s = 0;
+  for (int64_t i = threadIdx.x; i < d; i += 256) s += row[i];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  __shared__ uint32_t part[4];
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) nb[b] = part[0] + part[1] + part[2] + part[3];
+}
+
+// rowpart as written by fold_counts_kernel: [3^n / rows][runs][rows].
+__global__ void check_rows_kernel(const uint32_t* __restrict__ rowpart, int64_t rows, int64_t runs,
+                                  const uint32_t* __restrict__ nb, uint64_t shots,
+                                  int64_t nbases, uint32_t* __restrict__ flags) {
+  const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (b >= nbases) return;
+  const int64_t grp = b / rows, j = b % rows;
+  uint64_t tot = 0;
+  for (int64_t r = 0; r < runs; ++r) tot += rowpart[(grp * runs + r) * rows + j];
+  const uint64_t want = shots ? shots : (uint64_t)nb[b];
+  if (tot != want) atomicOr(flags, (uint32_t)FLAG_SHOTS);
+  if (!shots && want == 0) atomicOr(flags, (uint32_t)FLAG_EMPTY);
+}
+
+// ---------------------------------------------------------------------------------
+// Signed outcome sums of selected rows (verification entry): the low Q bits with the
+// same register/lane butterflies as pass 1, the high bits in LDS.  One block per row.
+template <int Q>
+__global__ __launch_bounds__(256) void signed_sums_kernel(const uint16_t* __restrict__ counts,
+                                                          int n, const int64_t* __restrict__ bases,
+                                                          int32_t* __restrict__ out,
+                                                          uint32_t* __restrict__ flags) {
+  using G = Fold1Geom<Q>;
+  extern __shared__ int32_t srow[];
+  const int64_t d = (int64_t)1 << n;
+  const int64_t b = bases[blockIdx.x];
+  const bool ok = b >= 0 && b < ipow3(n);
+  if (!ok && threadIdx.x == 0) atomicOr(flags, (uint32_t)FLAG_ARG);
+  const int tid = threadIdx.x;
+  const int grp = tid / G::LPC, lam = tid % G::LPC;
+  constexpr int GROUPS = 256 / G::LPC;
+  const int64_t nchunks = d >> Q;
+  for (int64_t ch = grp; ch < nchunks; ch += GROUPS) {
+    int32_t x[G::V];
+    if (ok) load_counts<G::V>(counts + b * d + (ch << Q) + lam * G::V, x);
+    else
+      for (int v = 0; v < G::V; ++v) x[v] = 0;
+    wht_regs<G::LB>(x);
+    wht_lanes<G::LL, G::V>(x, lam);
+    for (int v = 0; v < G::V; ++v) srow[(ch << Q) + lam * G::V + v] = x[v];
+  }
+  __syncthreads();
+  for (int bit = Q; bit < n; ++bit) {
+    for (int64_t t = tid; t < d / 2; t += 256) {
+      const int64_t lo = ((t >> bit) << (bit + 1)) | (t & (((int64_t)1 << bit) - 1));
+      const int64_t hi = lo | ((int64_t)1 << bit);
+      const int32_t a = srow[lo], c = srow[hi];
+      srow[lo] = a + c;
+      srow[hi] = a - c;
+    }
+    __syncthreads();
+  }
+  for (int64_t t = tid; t < d; t += 256) out[(int64_t)blockIdx.x * d + t] = srow[t];
+}
+
+// ---------------------------------------------------------------------------------
+// Step (ii).
+
+// (-i)^k applied to (re, im).
+__device__ __forceinline__ void mul_neg_i_pow(int k, double& re, double& im) {
+  const double r = re, i = im;
+  switch (k & 3) {
+    case 0: break;
+    case 1: re = i; im = -r; break;
+    case 2: re = -r; im = -i; break;
+    default: re = -i; im = r; break;
+  }
+}
+
+template <typename OutT>
+__device__ __forceinline__ void store_complex(void* base, int64_t idx, double re, double im) {
+  if constexpr (sizeof(OutT) == 8) {
+    reinterpret_cast<double2*>(base)[idx] = make_double2(re, im);
+  } else {
+    reinterpret_cast<float2*>(base)[idx] = make_float2((float)re, (float)im);
+  }
+}
+
+// Transform the low J qubits of one 4^J block of coefficients (block = high letters).
+// FINAL (J == n): writes mu directly.  Otherwise tmp[a_hi][r_lo][x_lo] (complex128).
+template <int J, bool FINAL, typename OutT>
+__global__ __launch_bounds__(256) void rho_low_kernel(const double* __restrict__ coef,
+                                                      void* __restrict__ out, int n) {
+  constexpr int D = 1 << J;
+  constexpr int NN = D * D;
+  __shared__ double re[NN], im[NN];  // [x][z], then [x][r]
+  const int64_t a_hi = blockIdx.x;
+  const double* __restrict__ e = coef + a_hi * NN;
+  for (int t = threadIdx.x; t < NN; t += 256) {
+    int x = 0, z = 0, ny = 0;
+#pragma unroll
+    for (int p = 0; p < J; ++p) {
+      const int dgt = (t >> (2 * p)) & 3;
+      x |= (dgt == 1 || dgt == 2) << p;
+      z |= (dgt >= 2) << p;
+      ny += dgt == 2;
+    }
+    double vr = e[t], vi = 0.0;
+    mul_neg_i_pow(ny, vr, vi);
+    re[x * D + z] = vr;
+    im[x * D + z] = vi;
+  }
+  __syncthreads();
+#pragma unroll 1
+  for (int bit = 0; bit < J; ++bit) {
+    for (int t = threadIdx.x; t < NN / 2; t += 256) {
+      const int x = t / (D / 2), k = t % (D / 2);
+      const int lo = ((k >> bit) << (bit + 1)) | (k & ((1 << bit) - 1));
+      const int hi = lo | (1 << bit);
+      const double a = re[x * D + lo], b = re[x * D + hi];
+      re[x * D + lo] = a + b;
+      re[x * D + hi] = a - b;
+      const double c = im[x * D + lo], f = im[x * D + hi];
+      im[x * D + lo] = c + f;
+      im[x * D + hi] = c - f;
+    }
+    __syncthreads();
+  }
+  if constexpr (FINAL) {
+    const double scale = ldexp(1.0, -J);  // 2^-n with n == J
+    for (int t = threadIdx.x; t < NN; t += 256) {
+      const int r = t / D, c = t % D, x = r ^ c;
+      store_complex<OutT>(out, t, re[x * D + r] * scale, im[x * D + r] * scale);
+    }
+  } else {
+    double2* tmp = static_cast<double2*>(out) + a_hi * NN;
+    for (int t = threadIdx.x; t < NN; t += 256) {
+      const int r = t / D, x = t % D;
+      tmp[t] = make_double2(re[x * D + r], im[x * D + r]);
+    }
+  }
+}
+
+// Transform the high H = n - J qubits and write mu row-major.  Block -> (x_hi, r_lo,
+// block of XB consecutive x_lo); the XB entries of a row are adjacent in memory.
+template <int XB, int HMAX, typename OutT>
+__global__ __launch_bounds__(256) void rho_high_kernel(const double2* __restrict__ tmp,
+                                                       void* __restrict__ rho, int n, int J) {
+  __shared__ double re[XB << HMAX], im[XB << HMAX];  // [xo][z]
+  const int H = n - J;
+  const int NH = 1 << H;
+  const int D = 1 << J;
+  int64_t bid = blockIdx.x;
+  const int xblk = (int)(bid % (D / XB));
+  bid /= (D / XB);
+  const int r_lo = (int)(bid % D);
+  const int64_t x_hi = bid / D;
+  const int tile = NH * XB;
+  for (int t = threadIdx.x; t < tile; t += 256) {
+    const int z = t / XB, xo = t % XB;
+    const int x_lo = xblk * XB + xo;
+    int64_t a_hi = 0;
+    for (int p = H - 1; p >= 0; --p) {
+      const int xb = (x_hi >> p) & 1, zb = (z >> p) & 1;
+      a_hi = a_hi * 4 + (xb ? (zb ? 2 : 1) : (zb ? 3 : 0));
+    }
+    const double2 v = tmp[(a_hi * D + r_lo) * D + x_lo];
+    double vr = v.x, vi = v.y;
+    mul_neg_i_pow(__popc((unsigned)(x_hi & z)), vr, vi);
+    re[xo * NH + z] = vr;
+    im[xo * NH + z] = vi;
+  }
+  __syncthreads();
+  for (int bit = 0; bit < H; ++bit) {
+    for (int t = threadIdx.x; t < tile / 2; t += 256) {
+      const int xo = t / (NH / 2), k = t % (NH / 2);
+      const int lo = ((k >> bit) << (bit + 1)) | (k & ((1 << bit) - 1));
+      const int hi = lo | (1 << bit);
+      const double a = re[xo * NH + lo], b = re[xo * NH + hi];
+      re[xo * NH + lo] = a + b;
+      re[xo * NH + hi] = a - b;
+      const double c = im[xo * NH + lo], f = im[xo * NH + hi];
+      im[xo * NH + lo] = c + f;
+      im[xo * NH + hi] = c - f;
+    }
+    __syncthreads();
+  }
+  const double scale = ldexp(1.0, -n);
+  const int64_t dn = (int64_t)1 << n;
+  for (int t = threadIdx.x; t < tile; t += 256) {
+    const int r_hi = t / XB, xo = t % XB;
+    const int x_lo = xblk * XB + xo;
+    const int64_t row = ((int64_t)r_hi << J) | r_lo;
+    const int64_t col = ((int64_t)(r_hi ^ x_hi) << J) | (r_lo ^ x_lo);
+    store_complex<OutT>(rho, row * dn + col, re[xo * NH + r_hi] * scale, im[xo * NH + r_hi] * scale);
+  }
+}
+
+}  // namespace lre

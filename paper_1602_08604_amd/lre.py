@@ -1,0 +1,213 @@
+"""Python binding of the gfx950 LRE library (include/lre.h) via ctypes.
+
+Argument marshalling only: tensors are checked for dtype, device, shape and
+contiguity, and their device pointers are handed to the C ABI together with the
+current HIP stream.  Every step of the computation runs in the HIP kernels of
+liblre.so; there is no fallback, and a missing library raises LreError.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "_lib", "liblre.so")
+HEADER_PATH = os.path.join(os.path.dirname(_PKG), "include", "lre.h")
+
+LRE_OK = 0
+LRE_E_ARG = 1
+LRE_E_WORKSPACE = 2
+LRE_E_HIP = 3
+LRE_E_SHOTS = 4
+LRE_E_EMPTY_BASIS = 5
+LRE_E_UNSUPPORTED = 6
+
+LRE_NO_RHO = 0x1
+LRE_RHO_FP32 = 0x2
+LRE_WHT_MFMA = 0x4
+LRE_MAX_QUBITS = 14
+
+
+class LreError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        msg = status_str(status) if _lib_handle is not None else f"status {status}"
+        super().__init__(f"{what}: {msg}" if what else msg)
+
+
+_lib_handle = None
+
+
+def lib():
+    """The loaded liblre.so (raises LreError if it has not been built)."""
+    global _lib_handle
+    if _lib_handle is None:
+        if not os.path.exists(LIB_PATH):
+            raise LreError(LRE_E_UNSUPPORTED, f"HIP library not built: {LIB_PATH} "
+                                              "(run python -m paper_1602_08604_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I, U32, U64, SZ, I64 = (ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint64,
+                                   ctypes.c_size_t, ctypes.c_int64)
+        L.lre_create.argtypes = [ctypes.POINTER(P), I]
+        L.lre_create.restype = I
+        L.lre_destroy.argtypes = [P]
+        L.lre_destroy.restype = None
+        L.lre_status_str.argtypes = [I]
+        L.lre_status_str.restype = ctypes.c_char_p
+        L.lre_workspace_bytes.argtypes = [I, U64, U32]
+        L.lre_workspace_bytes.restype = SZ
+        L.lre_estimate.argtypes = [P, I, P, U64, P, P, P, P, SZ, U32, P]
+        L.lre_estimate.restype = I
+        L.lre_check.argtypes = [P, P]
+        L.lre_check.restype = I
+        L.lre_pauli_sums.argtypes = [P, I, P, U64, P, P, SZ, U32, P]
+        L.lre_pauli_sums.restype = I
+        L.lre_signed_sums.argtypes = [P, I, P, P, I64, P, U32, P]
+        L.lre_signed_sums.restype = I
+        L.lre_set_stage_events.argtypes = [P, ctypes.POINTER(P), I]
+        L.lre_set_stage_events.restype = I
+        _lib_handle = L
+    return _lib_handle
+
+
+def declared_symbols(header: str = HEADER_PATH):
+    """Function names declared in include/lre.h."""
+    with open(header) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"^\s*(?:[\w\s\*]+?)\b(lre_\w+)\s*\(", text, re.M)))
+
+
+def status_str(status: int) -> str:
+    return lib().lre_status_str(int(status)).decode()
+
+
+def _ok(status: int, what: str):
+    if status != LRE_OK:
+        raise LreError(status, what)
+
+
+_contexts: dict[int, int] = {}
+
+
+def context(device: int | None = None) -> int:
+    """lre_ctx* for a device (created once per process)."""
+    dev = torch.cuda.current_device() if device is None else int(device)
+    if dev not in _contexts:
+        h = ctypes.c_void_p()
+        _ok(lib().lre_create(ctypes.byref(h), dev), "lre_create")
+        _contexts[dev] = h.value
+    return _contexts[dev]
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _num_qubits(counts: torch.Tensor) -> int:
+    if counts.dim() != 2:
+        raise ValueError("counts must be 2-D (3^n, 2^n)")
+    d = counts.shape[1]
+    n = d.bit_length() - 1
+    if d != 1 << n or counts.shape[0] != 3 ** n or not 1 <= n <= LRE_MAX_QUBITS:
+        raise ValueError(f"counts shape {tuple(counts.shape)} is not (3^n, 2^n) with 1 <= n <= 14")
+    return n
+
+
+def _check_counts(counts: torch.Tensor) -> int:
+    if counts.dtype not in (torch.uint16, torch.int16):
+        raise TypeError("counts must be uint16 (int16 is reinterpreted bitwise)")
+    if not counts.is_cuda or not counts.is_contiguous():
+        raise ValueError("counts must be a contiguous device tensor")
+    return _num_qubits(counts)
+
+
+def workspace_bytes(n: int, shots: int, flags: int = 0) -> int:
+    return int(lib().lre_workspace_bytes(int(n), int(shots), int(flags)))
+
+
+def estimate(counts: torch.Tensor, shots: int, n_per_basis: torch.Tensor | None = None,
+             flags: int = 0, coef: torch.Tensor | None = None, rho: torch.Tensor | None = None,
+             workspace: torch.Tensor | None = None, check: bool = True):
+    """lre_estimate: (coef float64 [4^n], rho complex [2^n, 2^n] or None)."""
+    n = _check_counts(counts)
+    dev = counts.device
+    d = 1 << n
+    if coef is None:
+        coef = torch.empty(4 ** n, dtype=torch.float64, device=dev)
+    want_rho = not (flags & LRE_NO_RHO)
+    if want_rho and rho is None:
+        rho = torch.empty((d, d), dtype=torch.complex64 if flags & LRE_RHO_FP32 else torch.complex128,
+                          device=dev)
+    if n_per_basis is not None:
+        if n_per_basis.dtype not in (torch.int32, torch.uint32) or not n_per_basis.is_cuda \
+                or n_per_basis.numel() != 3 ** n or not n_per_basis.is_contiguous():
+            raise ValueError("n_per_basis must be a contiguous 32-bit device tensor of length 3^n")
+    wsb = workspace_bytes(n, shots, flags)
+    if workspace is None:
+        workspace = torch.empty(max(wsb, 1), dtype=torch.uint8, device=dev)
+    st = lib().lre_estimate(
+        ctypes.c_void_p(context(dev.index)), n, ctypes.c_void_p(counts.data_ptr()), int(shots),
+        ctypes.c_void_p(n_per_basis.data_ptr() if n_per_basis is not None else None),
+        ctypes.c_void_p(coef.data_ptr()), ctypes.c_void_p(rho.data_ptr() if want_rho else None),
+        ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), int(flags),
+        ctypes.c_void_p(_stream(dev)))
+    _ok(st, "lre_estimate")
+    if check:
+        check_flags(dev)
+    return coef, rho
+
+
+def check_flags(device=None):
+    """lre_check: synchronise the current stream and raise on a data error flag."""
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    _ok(lib().lre_check(ctypes.c_void_p(context(dev.index)), ctypes.c_void_p(_stream(dev))), "lre_check")
+
+
+def pauli_sums(counts: torch.Tensor, shots: int, flags: int = 0, T: torch.Tensor | None = None,
+               workspace: torch.Tensor | None = None, check: bool = True) -> torch.Tensor:
+    """lre_pauli_sums: exact int64 numerators T_i of eq. (3) (uniform shots)."""
+    n = _check_counts(counts)
+    dev = counts.device
+    if T is None:
+        T = torch.empty(4 ** n, dtype=torch.int64, device=dev)
+    wsb = workspace_bytes(n, shots, flags | LRE_NO_RHO)
+    if workspace is None:
+        workspace = torch.empty(max(wsb, 1), dtype=torch.uint8, device=dev)
+    st = lib().lre_pauli_sums(ctypes.c_void_p(context(dev.index)), n, ctypes.c_void_p(counts.data_ptr()),
+                              int(shots), ctypes.c_void_p(T.data_ptr()),
+                              ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), int(flags),
+                              ctypes.c_void_p(_stream(dev)))
+    _ok(st, "lre_pauli_sums")
+    if check:
+        check_flags(dev)
+    return T
+
+
+def signed_sums(counts: torch.Tensor, bases: torch.Tensor, flags: int = 0,
+                check: bool = True) -> torch.Tensor:
+    """lre_signed_sums: int32 [len(bases), 2^n] Walsh sums of the selected rows."""
+    n = _check_counts(counts)
+    dev = counts.device
+    if bases.dtype != torch.int64 or not bases.is_cuda or not bases.is_contiguous():
+        raise ValueError("bases must be a contiguous int64 device tensor")
+    out = torch.empty((bases.numel(), 1 << n), dtype=torch.int32, device=dev)
+    st = lib().lre_signed_sums(ctypes.c_void_p(context(dev.index)), n, ctypes.c_void_p(counts.data_ptr()),
+                               ctypes.c_void_p(bases.data_ptr()), bases.numel(),
+                               ctypes.c_void_p(out.data_ptr()), int(flags), ctypes.c_void_p(_stream(dev)))
+    _ok(st, "lre_signed_sums")
+    if check:
+        check_flags(dev)
+    return out
+
+
+def set_stage_events(events, device=None):
+    """lre_set_stage_events: raw hipEvent_t handles (ints) or None to disable."""
+    ctx = ctypes.c_void_p(context(device))
+    if not events:
+        _ok(lib().lre_set_stage_events(ctx, None, 0), "lre_set_stage_events")
+        return
+    arr = (ctypes.c_void_p * len(events))(*events)
+    _ok(lib().lre_set_stage_events(ctx, arr, len(events)), "lre_set_stage_events")

@@ -7,8 +7,6 @@ eq. (3) and the matrix sum of eq. (4).  Sizes are exponential, so n <= 4.
 """
 from __future__ import annotations
 
-import itertools
-
 import numpy as np
 
 SIGMA = [np.eye(2, dtype=np.complex128),
@@ -88,14 +86,15 @@ def ghz_expectations(n, p_dep=0.0):
     """Closed form for rho = (1-p)|GHZ_n><GHZ_n| + p I/2^n:  the Pauli string over {I,Z}
     with an even number of Z has expectation 1; a string over {X,Y} with an even number
     of Y has (-1)^{#Y/2}; every other string 0.  Non-identity values scale by (1-p)."""
+    i = np.arange(4 ** n)
+    letters = np.stack([(i >> (2 * (n - 1 - k))) & 3 for k in range(n)], axis=1)
+    nz = np.sum(letters == 3, axis=1)
+    ny = np.sum(letters == 2, axis=1)
+    iz = np.all((letters == 0) | (letters == 3), axis=1) & (nz % 2 == 0)
+    xy = np.all((letters == 1) | (letters == 2), axis=1) & (ny % 2 == 0)
     out = np.zeros(4 ** n)
-    for i, letters in enumerate(itertools.product(range(4), repeat=n)):
-        nz = sum(1 for a in letters if a == 3)
-        ny = sum(1 for a in letters if a == 2)
-        if all(a in (0, 3) for a in letters) and nz % 2 == 0:
-            out[i] = 1.0
-        elif all(a in (1, 2) for a in letters) and ny % 2 == 0:
-            out[i] = (-1.0) ** (ny // 2)
+    out[iz] = 1.0
+    out[xy] = np.where((ny[xy] // 2) % 2 == 0, 1.0, -1.0)
     out[1:] *= (1.0 - p_dep)
     return out
 

@@ -57,3 +57,11 @@ def test_multinomial_rows_sum_to_shots():
     shots = rng.integers(100, 10_000, size=81)
     c = ti.multinomial_counts(p, shots, rng)
     assert np.array_equal(c.sum(axis=1), shots)
+
+
+def test_philox_c_twin_matches_numpy_twin():
+    bases = np.array([0, 1, 2, 12345, 4782968])
+    c, nb = ti.philox_counts_rows_fast(14, 987654321, bases)
+    ref = ti.philox_counts_rows(14, 987654321, bases)
+    np.testing.assert_array_equal(c, ref)
+    np.testing.assert_array_equal(nb, ref.sum(axis=1))

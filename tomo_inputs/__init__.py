@@ -13,7 +13,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .philox import philox4x32_10, philox_counts_rows  # noqa: F401
+from .philox import philox4x32_10, philox_counts_rows, philox_counts_rows_fast  # noqa: F401
 
 # Rows of U_b are the bras <psi_{b,s}| of the eigenvectors of sigma_{b+1}, so that
 # (U_b psi)_s = <psi_{b,s}|psi> is the amplitude of outcome s.

@@ -59,3 +59,27 @@ def philox_counts_rows(n: int, seed: int, bases) -> np.ndarray:
                                 (b >> np.uint64(32)).astype(np.uint32), np.uint32(0), k0, k1)
     c = (x0.astype(np.uint64) * np.uint64(COUNT_LEVELS)) >> np.uint64(32)
     return c.astype(np.uint16)
+
+
+_clib = None
+
+
+def philox_counts_rows_fast(n: int, seed: int, bases) -> tuple[np.ndarray, np.ndarray]:
+    """Same rows as philox_counts_rows, from the OpenMP C twin; also returns the row totals.
+    Builds the C twin on first use."""
+    global _clib
+    import ctypes
+    if _clib is None:
+        from .build import build_cpu
+        L = ctypes.CDLL(build_cpu(force=False))
+        L.tomo_philox_rows.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_void_p,
+                                       ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]
+        L.tomo_philox_rows.restype = ctypes.c_int
+        _clib = L
+    b = np.ascontiguousarray(bases, dtype=np.int64)
+    out = np.empty((len(b), 2 ** n), dtype=np.uint16)
+    nb = np.empty(len(b), dtype=np.uint32)
+    rc = _clib.tomo_philox_rows(n, seed, b.ctypes.data, len(b), out.ctypes.data, nb.ctypes.data)
+    if rc:
+        raise RuntimeError("tomo_philox_rows failed")
+    return out, nb
