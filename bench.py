@@ -158,8 +158,8 @@ def cpu_baseline(workload, n, shots, counts_dev, coef_dev, budget_s=12.0):
         oracle.coefs(n, c, shots, idx=idx)
         t_i = time.perf_counter() - t0
         visits_i = int(np.sum(3.0 ** (n - w))) * 2 ** n
-        sample = f"4096 random coefficients of the full count tensor"
-        threads = os.cpu_count()
+        sample = "4096 random coefficients of the full count tensor"
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count()))
     # step (ii): sampled entries of eq. (4) on the GPU coefficients
     coef = coef_dev.cpu().numpy() if workload != "n14" else None
     t_ii, visits_ii = 0.0, 0

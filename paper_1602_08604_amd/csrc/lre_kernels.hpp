@@ -113,18 +113,66 @@ __device__ __forceinline__ void wht_regs(T* x) {
   }
 }
 
-// Butterflies across the low NL bits of the lane index (partners within a group of
-// 2^NL consecutive lanes).  The lower lane keeps x + partner, the upper partner - x.
+// Butterflies across the NL low bits of the lane index (groups of 2^NL <= 16
+// consecutive lanes), on the VALU through DPP (no LDS traffic).  gfx9 DPP offers
+// quad_perm (partners lane^1, lane^2 within a quad), row_half_mirror (lane^7 within
+// 8) and row_mirror (lane^15 within 16).  A stage along direction v pairs lane i with
+// i^v; the member with odd parity of (i & U) keeps partner - x, the other x + partner.
+// With the directions and masks U below the stages compose to the exact Walsh-Hadamard
+// transform over the lane bits with the output index relabelled by a linear map
+// sigma (checked exhaustively on the host): lane l ends up holding Walsh index
+// lane_walsh<NL>(l) for its lane bits.
+//   NL = 1, 2 : lane^1 (U = 1), lane^2 (U = 2)                  sigma = identity
+//   NL = 3    : lane^7 (U = 4), lane^1 (U = 5), lane^2 (U = 6)   sigma(1,2,4) = 5,6,7
+//   NL = 4    : lane^15 (U = 8), lane^7 (U = 12), lane^1 (U = 5), lane^2 (U = 6)
+//                                                               sigma(1,2,4,8) = 5,6,15,4
+template <int NL>
+__host__ __device__ constexpr int lane_walsh(int l) {
+  if constexpr (NL <= 2) {
+    return l;
+  } else if constexpr (NL == 3) {
+    return ((l & 1) ? 5 : 0) ^ ((l & 2) ? 6 : 0) ^ ((l & 4) ? 7 : 0);
+  } else {
+    return ((l & 1) ? 5 : 0) ^ ((l & 2) ? 6 : 0) ^ ((l & 4) ? 15 : 0) ^ ((l & 8) ? 4 : 0);
+  }
+}
+
+constexpr int kDppQuadXor1 = 0xB1;    // quad_perm [1,0,3,2]
+constexpr int kDppQuadXor2 = 0x4E;    // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141; // row_half_mirror
+constexpr int kDppMirror = 0x140;     // row_mirror
+
+// Values here are partial Walsh sums of at most 2^7 uint16 counts, |x| < 2^23, so the
+// +-1 weighting is a 24-bit signed multiply-add (v_mad_i32_i24) behind the DPP move.
+template <int CTRL, int V>
+__device__ __forceinline__ void lane_stage(int32_t* x, int lam, int umask) {
+  int32_t sgn = (__popc((unsigned)(lam & umask)) & 1) ? -1 : 1;  // partner - x for the odd member
+  // Hide the +-1 range from the optimiser, which would otherwise expand the multiply
+  // into select/negate sequences (3-4 VALU ops instead of one v_mad_i32_i24).
+  asm volatile("" : "+v"(sgn));
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    const int32_t p = __builtin_amdgcn_mov_dpp(x[v], CTRL, 0xF, 0xF, true);
+    x[v] = __mul24(x[v], sgn) + p;
+  }
+}
+
 template <int NL, int V>
 __device__ __forceinline__ void wht_lanes(int32_t* x, int lam) {
-#pragma unroll
-  for (int bit = 0; bit < NL; ++bit) {
-    const bool upper = (lam >> bit) & 1;
-#pragma unroll
-    for (int v = 0; v < V; ++v) {
-      int32_t p = __shfl_xor(x[v], 1 << bit, 64);
-      x[v] = upper ? (p - x[v]) : (x[v] + p);
-    }
+  if constexpr (NL == 1) {
+    lane_stage<kDppQuadXor1, V>(x, lam, 1);
+  } else if constexpr (NL == 2) {
+    lane_stage<kDppQuadXor1, V>(x, lam, 1);
+    lane_stage<kDppQuadXor2, V>(x, lam, 2);
+  } else if constexpr (NL == 3) {
+    lane_stage<kDppHalfMirror, V>(x, lam, 4);
+    lane_stage<kDppQuadXor1, V>(x, lam, 5);
+    lane_stage<kDppQuadXor2, V>(x, lam, 6);
+  } else if constexpr (NL == 4) {
+    lane_stage<kDppMirror, V>(x, lam, 8);
+    lane_stage<kDppHalfMirror, V>(x, lam, 12);
+    lane_stage<kDppQuadXor1, V>(x, lam, 5);
+    lane_stage<kDppQuadXor2, V>(x, lam, 6);
   }
 }
 
@@ -145,6 +193,17 @@ struct Fold1Geom {
   static constexpr int NACC = (int)ipow4(Q);        // accumulators per tile
   static constexpr int NROWS = (int)ipow3(Q);       // rows per tile
 };
+
+// LDS slot of Pauli index a (Q base-4 digits) in the counts-pass accumulator:
+// [letters of positions < RD][positions RD..LB-1][positions LB..Q-1], most significant
+// first, i.e. the three digit fields of a in reverse order.
+template <int Q, int RD, int LB>
+__device__ __forceinline__ uint32_t acc_slot(uint32_t a) {
+  const uint32_t ar = a & ((1u << (2 * RD)) - 1);
+  const uint32_t ureg = (a >> (2 * RD)) & ((1u << (2 * (LB - RD))) - 1);
+  const uint32_t ulane = a >> (2 * LB);
+  return (ar << (2 * (Q - RD))) | (ureg << (2 * (Q - LB))) | ulane;
+}
 
 template <int V>
 __device__ __forceinline__ void load_counts(const uint16_t* __restrict__ p, int32_t* x) {
@@ -260,36 +319,41 @@ __global__ __launch_bounds__(THREADS) void fold_counts_kernel(
         });
       });
 
-      // Accumulator address: letters of the positions above RD come from the Walsh
-      // bits (register bits RD..LB-1, lane bits) and the basis digits of the row-set.
-      uint32_t base = 0;
-      uint32_t tv[G::LB - G::RD > 0 ? G::LB - G::RD : 1] = {};
+      // Accumulator slot.  Positions >= RD get the letter (b_p + 1) where Walsh bit p is
+      // set, I otherwise; Walsh bits RD..LB-1 are register bits (vh), bits LB..Q-1 come
+      // from the lane (relabelled by lane_walsh).  LDS layout (acc_slot): the lane-owned
+      // letters occupy the low bits so that the lanes of one atomic spread over banks.
+      const int lw = lane_walsh<G::LL>(lam);
+      uint32_t ulane = 0;
+      uint32_t treg[G::LB - G::RD > 0 ? G::LB - G::RD : 1] = {};
       {
         int t = rs;
         StaticFor<0, Q - G::RD>::run([&](auto jc) __attribute__((always_inline)) {
           constexpr int j = decltype(jc)::value;
           constexpr int p = G::RD + j;
-          const uint32_t term = (uint32_t)(t % 3 + 1) << (2 * p);
+          const uint32_t dgt = (uint32_t)(t % 3 + 1);
           t /= 3;
-          if constexpr (p < G::LB) tv[j] = term;
-          else if ((lam >> (p - G::LB)) & 1) base += term;
+          if constexpr (p < G::LB) treg[j] = dgt << (2 * (Q - G::LB + j));
+          else if ((lw >> (p - G::LB)) & 1) ulane += dgt << (2 * (p - G::LB));
         });
       }
 #pragma unroll
       for (int vh = 0; vh < G::VH; ++vh) {
-        uint32_t off = base;
+        uint32_t off = ulane;
 #pragma unroll
         for (int q = 0; q < G::LB - G::RD; ++q)
-          if ((vh >> q) & 1) off += tv[q];
+          if ((vh >> q) & 1) off += treg[q];
 #pragma unroll
-        for (int ar = 0; ar < G::NAR; ++ar) atomicAdd(&acc[off + ar], o[vh][ar]);
+        for (int ar = 0; ar < G::NAR; ++ar)
+          atomicAdd(&acc[off + ((uint32_t)ar << (2 * (Q - G::RD)))], o[vh][ar]);
       }
     }
     __syncthreads();
 
     for (int i = tid; i < G::NACC; i += THREADS) {
-      const Acc v = acc[i];
-      acc[i] = Acc(0);
+      const uint32_t slot = acc_slot<Q, G::RD, G::LB>((uint32_t)i);
+      const Acc v = acc[slot];
+      acc[slot] = Acc(0);
       if constexpr (MODE == Out::Partial) {
         static_cast<Acc*>(out)[(b_hi * n_shi + s_hi) * G::NACC + i] = v;
       } else if constexpr (MODE == Out::CoefUniform) {
@@ -436,7 +500,7 @@ __global__ __launch_bounds__(256) void signed_sums_kernel(const uint16_t* __rest
       for (int v = 0; v < G::V; ++v) x[v] = 0;
     wht_regs<G::LB>(x);
     wht_lanes<G::LL, G::V>(x, lam);
-    for (int v = 0; v < G::V; ++v) srow[(ch << Q) + lam * G::V + v] = x[v];
+    for (int v = 0; v < G::V; ++v) srow[(ch << Q) + lane_walsh<G::LL>(lam) * G::V + v] = x[v];
   }
   __syncthreads();
   for (int bit = Q; bit < n; ++bit) {
