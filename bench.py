@@ -188,6 +188,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="n14", choices=["n14", "n12", "n8"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--wht", default="mfma", choices=["mfma", "plain"],
+                    help="counts-pass Walsh transform for the headline run; the other one is "
+                         "timed too for the MFMA-vs-plain ratio")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -209,30 +212,41 @@ def main():
     print(f"[bench] workload {args.workload}: generated in {t_gen:.1f} s; workspace "
           f"{ws.numel() / 1e9:.2f} GB", file=sys.stderr, flush=True)
 
-    def step():
-        lre.estimate(counts, shots, n_per_basis=nb, coef=coef, rho=rho, workspace=ws, check=False)
+    def timed(flags):
+        def step():
+            lre.estimate(counts, shots, n_per_basis=nb, coef=coef, rho=rho, workspace=ws,
+                         flags=flags, check=False)
 
-    for _ in range(args.warmup):
-        step()
-    lre.check_flags("cuda:0")
-    ev = StageEvents(args.steps)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        lre.set_stage_events(ev.ev[k])
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    lre.set_stage_events(None)
-    lre.check_flags("cuda:0")
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    pass1 = [ev.ms(k, 0, 1) for k in range(args.steps)]
-    step_i = [ev.ms(k, 0, 2) for k in range(args.steps)]
-    step_ii = [ev.ms(k, 2, 3) for k in range(args.steps)]
-    ev.close()
-    print(f"[bench] {args.steps} steps: {ms_step:.3f} ms/step wall; counts pass "
-          f"{sum(pass1) / len(pass1):.3f} ms, step (i) {sum(step_i) / len(step_i):.3f} ms, "
-          f"step (ii) {sum(step_ii) / len(step_ii):.3f} ms", file=sys.stderr, flush=True)
+        for _ in range(args.warmup):
+            step()
+        lre.check_flags("cuda:0")
+        ev = StageEvents(args.steps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            lre.set_stage_events(ev.ev[k])
+            step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        lre.set_stage_events(None)
+        lre.check_flags("cuda:0")
+        res = {"ms_step": (t1 - t0) * 1e3 / args.steps,
+               "pass1": [ev.ms(k, 0, 1) for k in range(args.steps)],
+               "step_i": [ev.ms(k, 0, 2) for k in range(args.steps)],
+               "step_ii": [ev.ms(k, 2, 3) for k in range(args.steps)]}
+        ev.close()
+        mean = lambda v: sum(v) / len(v)
+        print(f"[bench] flags={flags}: {args.steps} steps: {res['ms_step']:.3f} ms/step wall; counts pass "
+              f"{mean(res['pass1']):.3f} ms, step (i) {mean(res['step_i']):.3f} ms, "
+              f"step (ii) {mean(res['step_ii']):.3f} ms", file=sys.stderr, flush=True)
+        return res
+
+    mfma_ok = n >= 7
+    head_flags = lre.LRE_WHT_MFMA if (args.wht == "mfma" and mfma_ok) else 0
+    head = timed(head_flags)
+    other = timed(0 if head_flags else lre.LRE_WHT_MFMA) if mfma_ok else None
+    ms_step = head["ms_step"]
+    pass1, step_i, step_ii = head["pass1"], head["step_i"], head["step_ii"]
 
     n_counts = 3 ** n * d
     t_pass1 = sum(pass1) / len(pass1) / 1e3
@@ -253,7 +267,7 @@ def main():
         "dtype": "int32+f64",
         "data": "synthetic",
         "config": {"workload": desc, "n": n, "shots": shots if shots else "per-basis",
-                   "parallelism": "single GPU"},
+                   "wht": "int8-mfma" if head_flags else "plain-int32", "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "fold_counts_kernel (counts pass of step (i))",
@@ -262,8 +276,18 @@ def main():
         "step_ms": {"counts_pass": t_pass1 * 1e3, "step_i": sum(step_i) / len(step_i),
                     "step_ii": sum(step_ii) / len(step_ii)},
         "whole_step_hbm_frac": algo_bytes / (ms_step / 1e3) / (HBM_PEAK_GBS * 1e9),
+        "wht": "int8-mfma" if head_flags else "plain-int32",
         "mfma_vs_plain": None,
     }
+    if other is not None:
+        mfma, plain = (head, other) if head_flags else (other, head)
+        mean = lambda v: sum(v) / len(v)
+        out["mfma_vs_plain"] = {
+            "counts_pass_speedup": mean(plain["pass1"]) / mean(mfma["pass1"]),
+            "step_speedup": plain["ms_step"] / mfma["ms_step"],
+            "plain_counts_pass_ms": mean(plain["pass1"]), "mfma_counts_pass_ms": mean(mfma["pass1"]),
+            "plain_ms_per_step": plain["ms_step"], "mfma_ms_per_step": mfma["ms_step"],
+            "signed_sums": "bit-identical (tests/test_gpu_parity.py)"}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload, n, shots, counts, coef)
     print(json.dumps(out), flush=True)

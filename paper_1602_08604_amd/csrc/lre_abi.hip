@@ -170,6 +170,36 @@ bool fold1_q(Ty t, bool pb, Out m, const Fold1Args& a) {
   }
 }
 
+template <typename Acc, bool PB, Out M>
+void launch_fold1_mfma(const Fold1Args& a) {
+  constexpr int TH = sizeof(Acc) == 8 ? 512 : 256;
+  hipLaunchKernelGGL((fold_counts_mfma_kernel<TH, Acc, PB, M>), dim3((unsigned)a.blocks), dim3(TH), 0,
+                     a.st, a.counts, a.n, a.chunks, a.nb, a.out, a.rowpart, a.shots);
+}
+
+bool fold1_mfma(Ty t, bool pb, Out m, const Fold1Args& a) {
+  if (pb) {
+    if (m == Out::Partial) launch_fold1_mfma<double, true, Out::Partial>(a);
+    else if (m == Out::CoefPerBasis) launch_fold1_mfma<double, true, Out::CoefPerBasis>(a);
+    else return false;
+    return true;
+  }
+  if (t == Ty::U32) {
+    switch (m) {
+      case Out::Partial: launch_fold1_mfma<uint32_t, false, Out::Partial>(a); return true;
+      case Out::CoefUniform: launch_fold1_mfma<uint32_t, false, Out::CoefUniform>(a); return true;
+      case Out::PauliT: launch_fold1_mfma<uint32_t, false, Out::PauliT>(a); return true;
+      default: return false;
+    }
+  }
+  switch (m) {
+    case Out::Partial: launch_fold1_mfma<double, false, Out::Partial>(a); return true;
+    case Out::CoefUniform: launch_fold1_mfma<double, false, Out::CoefUniform>(a); return true;
+    case Out::PauliT: launch_fold1_mfma<double, false, Out::PauliT>(a); return true;
+    default: return false;
+  }
+}
+
 bool fold1(int q, Ty t, bool pb, Out m, const Fold1Args& a) {
   switch (q) {
     case 1: return fold1_q<1>(t, pb, m, a);
@@ -265,7 +295,8 @@ bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) %
 
 // Step (i) into `final_out` (coef or T) with final mode `fm`.
 lre_status run_step1(lre_ctx* ctx, const Plan& P, const uint16_t* counts, uint64_t shots,
-                     const uint32_t* nb_in, void* final_out, Out fm, char* ws, hipStream_t st) {
+                     const uint32_t* nb_in, void* final_out, Out fm, char* ws, hipStream_t st,
+                     bool mfma) {
   const int n = P.n;
   const int64_t nbases = ipow3(n);
   const uint32_t* nb = nb_in;
@@ -279,7 +310,9 @@ lre_status run_step1(lre_ctx* ctx, const Plan& P, const uint16_t* counts, uint64
   Fold1Args a1{counts, n, P.chunks, nb, nullptr, rowpart, shots, P.blocks1, st};
   const bool single = P.npass == 0;
   a1.out = single ? final_out : (void*)(ws + P.off_a);
-  if (!fold1(P.q1, P.t1, P.per_basis, single ? fm : Out::Partial, a1)) return LRE_E_UNSUPPORTED;
+  const bool ok = (mfma && P.q1 == 7) ? fold1_mfma(P.t1, P.per_basis, single ? fm : Out::Partial, a1)
+                                       : fold1(P.q1, P.t1, P.per_basis, single ? fm : Out::Partial, a1);
+  if (!ok) return LRE_E_UNSUPPORTED;
   if (hipGetLastError() != hipSuccess) return LRE_E_HIP;
   record_stage(ctx, 1, st);
 
@@ -366,7 +399,6 @@ lre_status lre_estimate(lre_ctx* ctx, int n, const uint16_t* counts, uint64_t sh
   if (!aligned(counts, 16) || !aligned(coef, 8)) return LRE_E_ARG;
   const bool want_rho = !(flags & LRE_NO_RHO);
   if (want_rho && (!rho || !aligned(rho, 16))) return LRE_E_ARG;
-  if (flags & LRE_WHT_MFMA) return LRE_E_UNSUPPORTED;
   Plan P;
   if (!make_plan(n, shots, flags, P)) return LRE_E_ARG;
   if (P.total && (!workspace || !aligned(workspace, 256))) return LRE_E_ARG;
@@ -378,7 +410,8 @@ lre_status lre_estimate(lre_ctx* ctx, int n, const uint16_t* counts, uint64_t sh
 
   record_stage(ctx, 0, st);
   lre_status s = run_step1(ctx, P, counts, shots, n_per_basis, coef,
-                           P.per_basis ? Out::CoefPerBasis : Out::CoefUniform, ws, st);
+                           P.per_basis ? Out::CoefPerBasis : Out::CoefUniform, ws, st,
+                           (flags & LRE_WHT_MFMA) != 0);
   if (s != LRE_OK) return s;
   record_stage(ctx, 2, st);
   if (want_rho) {
@@ -421,7 +454,6 @@ lre_status lre_pauli_sums(lre_ctx* ctx, int n, const uint16_t* counts, uint64_t 
   if (!ctx || !counts || !T || n < 1 || n > LRE_MAX_QUBITS || shots == 0) return LRE_E_ARG;
   if (flags & ~(LRE_NO_RHO | LRE_RHO_FP32 | LRE_WHT_MFMA)) return LRE_E_ARG;
   if (!aligned(counts, 16) || !aligned(T, 8)) return LRE_E_ARG;
-  if (flags & LRE_WHT_MFMA) return LRE_E_UNSUPPORTED;
   Plan P;
   if (!make_plan(n, shots, flags | LRE_NO_RHO, P)) return LRE_E_ARG;
   if (P.total && (!workspace || !aligned(workspace, 256))) return LRE_E_ARG;
@@ -429,7 +461,7 @@ lre_status lre_pauli_sums(lre_ctx* ctx, int n, const uint16_t* counts, uint64_t 
   DeviceGuard g(ctx->device);
   if (!g.ok) return LRE_E_HIP;
   return run_step1(ctx, P, counts, shots, nullptr, T, Out::PauliT, static_cast<char*>(workspace),
-                   static_cast<hipStream_t>(stream));
+                   static_cast<hipStream_t>(stream), (flags & LRE_WHT_MFMA) != 0);
 }
 
 lre_status lre_signed_sums(lre_ctx* ctx, int n, const uint16_t* counts, const int64_t* bases,

@@ -301,10 +301,9 @@ __global__ __launch_bounds__(THREADS) void fold_counts_kernel(
         Acc y[G::V];
         if constexpr (PER_BASIS) {
           const uint32_t N = nb[rowb + beta];
-          const double keep = N ? 1.0 : 0.0;  // empty basis: flagged by the row check
-          const double Nd = N ? (double)N : 1.0;
+          const double inv = N ? 1.0 / (double)N : 0.0;  // empty basis: flagged by the row check
 #pragma unroll
-          for (int v = 0; v < G::V; ++v) y[v] = keep * ((double)x[beta][v] / Nd);
+          for (int v = 0; v < G::V; ++v) y[v] = (double)x[beta][v] * inv;
         } else {
 #pragma unroll
           for (int v = 0; v < G::V; ++v) y[v] = to_acc<Acc>(x[beta][v]);
@@ -371,6 +370,223 @@ __global__ __launch_bounds__(THREADS) void fold_counts_kernel(
 
   uint32_t* __restrict__ rp = rowpart + (int64_t)blockIdx.x * G::NROWS;
   for (int i = tid; i < G::NROWS; i += THREADS) rp[i] = rs_acc[i];
+}
+
+// ---------------------------------------------------------------------------------
+// Counts pass on int8 MFMA (Q = 7 qubits per tile).  The Walsh-Hadamard transform over
+// the low 6 outcome bits of every basis row is a dense +-1 contraction,
+//   S[m][row] = sum_{s < 64} H64[m][s] c[row][s],
+// run as v_mfma_i32_16x16x64_i8 with A = four 16-row blocks of H64 and B = counts.
+// A uint16 count c = b0 + 256 b1 is fed as two signed byte limbs l0 = b0 - 128,
+// l1 = b1 - 128 (c = l0 + 256 l1 + 32896); the constant 32896 only reaches Walsh row 0
+// (the only row of H64 with a nonzero sum, 64), so
+//   S = D(l0) + 256 D(l1) + 32896 * 64 * [m == 0]      exactly, in int32.
+// Lane l of an MFMA holds B column n = l % 16 and 16 K slots; A row l % 16 with the same
+// 16 K slots (the K order is internal to the instruction and common to A and B).  The
+// result lane l holds rows 4 (l / 16) + r, r < 4, of column l % 16.
+// Columns are 16 row-sets; the 3 rows of the lowest basis digit are 3 MFMA tiles in
+// sequence, so the lowest qubit is folded in registers (and per-basis division by N_b
+// happens per row before any cross-row sum).  Outcome bit 6 is a second 64-count block
+// combined with one butterfly in registers.  The remaining 6 qubits are summed over
+// basis letters in the LDS accumulator (atomics), as in the plain kernel.
+typedef int lre_v4i __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ lre_v4i limb_pack(const uint32_t* w, uint32_t sel) {
+  lre_v4i o;
+  o.x = (int)(__builtin_amdgcn_perm(w[1], w[0], sel) ^ 0x80808080u);
+  o.y = (int)(__builtin_amdgcn_perm(w[3], w[2], sel) ^ 0x80808080u);
+  o.z = (int)(__builtin_amdgcn_perm(w[5], w[4], sel) ^ 0x80808080u);
+  o.w = (int)(__builtin_amdgcn_perm(w[7], w[6], sel) ^ 0x80808080u);
+  return o;
+}
+
+// LDS slot of a Pauli index a (7 digits) in the MFMA counts-pass accumulator:
+// [a_0][a_1][a_4][a_5][a_6][a_2][a_3] (most significant first) -- the digits that
+// come from lane bits (positions 2, 3) are the low bits.
+__device__ __forceinline__ uint32_t mfma_slot(uint32_t a) {
+  const uint32_t d0 = a & 3, d1 = (a >> 2) & 3, d2 = (a >> 4) & 3, d3 = (a >> 6) & 3;
+  const uint32_t d4 = (a >> 8) & 3, d5 = (a >> 10) & 3, d6 = (a >> 12) & 3;
+  return (d0 << 12) | (d1 << 10) | (d4 << 8) | (d5 << 6) | (d6 << 4) | (d2 << 2) | d3;
+}
+
+template <int THREADS, typename Acc, bool PER_BASIS, Out MODE>
+__global__ __launch_bounds__(THREADS) void fold_counts_mfma_kernel(
+    const uint16_t* __restrict__ counts, int n, int chunks, const uint32_t* __restrict__ nb,
+    void* __restrict__ out, uint32_t* __restrict__ rowpart, uint64_t shots) {
+  constexpr int Q = 7;
+  constexpr int NACC = 1 << (2 * Q);
+  constexpr int NROWS = 2187;   // 3^7
+  constexpr int NRS = 729;      // row-sets of 3 rows
+  constexpr int WAVES = THREADS / 64;
+  __shared__ Acc acc[NACC];
+  __shared__ uint32_t rs_acc[NROWS];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int col = lane & 15, g = lane >> 4;
+  const int64_t n_shi = (int64_t)1 << (n - Q);
+  const int64_t runs_per_row = n_shi / chunks;
+  const int64_t b_hi = blockIdx.x / runs_per_row;
+  const int64_t s_hi0 = (blockIdx.x % runs_per_row) * chunks;
+  const int64_t row0 = b_hi * NROWS;
+  const int64_t rowlen = (int64_t)1 << n;
+
+  // A operand: H64 rows 16 mb + col, K slots 16 g + j.
+  lre_v4i hA[4];
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb) {
+    const int m = 16 * mb + col;
+    int wv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      uint32_t wd = 0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int k = 16 * g + 4 * q + b;
+        const uint32_t v = (__popc((unsigned)(m & k)) & 1) ? 0xFFu : 0x01u;
+        wd |= v << (8 * b);
+      }
+      wv[q] = (int)wd;
+    }
+    hA[mb] = lre_v4i{wv[0], wv[1], wv[2], wv[3]};
+  }
+
+  for (int i = tid; i < NACC; i += THREADS) acc[i] = Acc(0);
+  for (int i = tid; i < NROWS; i += THREADS) rs_acc[i] = 0;
+  __syncthreads();
+
+  for (int c = 0; c < chunks; ++c) {
+    const int64_t s_hi = s_hi0 + c;
+    for (int rs0 = wave * 16; rs0 < NRS; rs0 += WAVES * 16) {
+      const int rs = rs0 + col;
+      const bool valid = rs < NRS;
+      // Basis digits of the row-set (positions 1..6) -> letter terms of the LDS slot.
+      uint32_t t1, t2, t3, t4, t5, t6;
+      {
+        int t = valid ? rs : 0;
+        t1 = (uint32_t)(t % 3 + 1) << 10; t /= 3;
+        t2 = (uint32_t)(t % 3 + 1) << 2;  t /= 3;
+        t3 = (uint32_t)(t % 3 + 1);       t /= 3;
+        t4 = (uint32_t)(t % 3 + 1) << 8;  t /= 3;
+        t5 = (uint32_t)(t % 3 + 1) << 6;  t /= 3;
+        t6 = (uint32_t)(t % 3 + 1) << 4;
+      }
+      const uint32_t ulane = ((g & 1) ? t2 : 0u) + ((g & 2) ? t3 : 0u);
+
+      Acc iacc[2][4][2];  // identity letter of qubit 0: [m6][mb][m1]
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) { iacc[a][b][0] = Acc(0); iacc[a][b][1] = Acc(0); }
+
+#pragma unroll 1
+      for (int beta = 0; beta < 3; ++beta) {
+        const int64_t row = row0 + 3 * (int64_t)rs + beta;
+        int32_t S[2][4][4];  // [outcome bit 6][mb][r]
+#pragma unroll
+        for (int sb = 0; sb < 2; ++sb) {
+          uint32_t w[8];
+          if (valid) {
+            const uint4* p = reinterpret_cast<const uint4*>(counts + row * rowlen + (s_hi << Q) + 64 * sb + 16 * g);
+            const uint4 u0 = p[0], u1 = p[1];
+            w[0] = u0.x; w[1] = u0.y; w[2] = u0.z; w[3] = u0.w;
+            w[4] = u1.x; w[5] = u1.y; w[6] = u1.z; w[7] = u1.w;
+          } else {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) w[k] = 0;
+          }
+          const lre_v4i l0 = limb_pack(w, 0x06040200u);
+          const lre_v4i l1 = limb_pack(w, 0x07050301u);
+#pragma unroll
+          for (int mb = 0; mb < 4; ++mb) {
+            const lre_v4i z = {0, 0, 0, 0};
+            const lre_v4i d0 = __builtin_amdgcn_mfma_i32_16x16x64_i8(hA[mb], l0, z, 0, 0, 0);
+            const lre_v4i d1 = __builtin_amdgcn_mfma_i32_16x16x64_i8(hA[mb], l1, z, 0, 0, 0);
+            S[sb][mb][0] = d0.x + (d1.x << 8);
+            S[sb][mb][1] = d0.y + (d1.y << 8);
+            S[sb][mb][2] = d0.z + (d1.z << 8);
+            S[sb][mb][3] = d0.w + (d1.w << 8);
+          }
+          if (g == 0) S[sb][0][0] += 32896 * 64;  // bias of the limb encoding (Walsh row 0)
+        }
+        // Butterfly on outcome bit 6: S[0] <- m6 = 0, S[1] <- m6 = 1.
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int32_t a = S[0][mb][r], b = S[1][mb][r];
+            S[0][mb][r] = a + b;
+            S[1][mb][r] = a - b;
+          }
+        // Row total (Walsh index 0) for the row check.
+        if (valid && g == 0) atomicAdd(&rs_acc[3 * rs + beta], (uint32_t)S[0][0][0]);
+
+        double inv = 1.0;
+        if constexpr (PER_BASIS) {
+          const uint32_t N = valid ? nb[row] : 1u;
+          inv = N ? 1.0 / (double)N : 0.0;  // empty basis: flagged by the row check
+        }
+        // Qubit 0: Walsh bit m0 = bit 0 of r.  m0 = 0 -> identity letter (sum over beta);
+        // m0 = 1 -> letter beta + 1, final for this qubit: add to LDS now.
+#pragma unroll
+        for (int m6 = 0; m6 < 2; ++m6)
+#pragma unroll
+          for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+            for (int m1 = 0; m1 < 2; ++m1) {
+              Acc v0, v1;
+              if constexpr (PER_BASIS) {
+                v0 = (double)S[m6][mb][2 * m1] * inv;
+                v1 = (double)S[m6][mb][2 * m1 + 1] * inv;
+              } else {
+                v0 = to_acc<Acc>(S[m6][mb][2 * m1]);
+                v1 = to_acc<Acc>(S[m6][mb][2 * m1 + 1]);
+              }
+              iacc[m6][mb][m1] += v0;
+              if (valid) {
+                const uint32_t slot = ulane + (m1 ? t1 : 0u) + ((mb & 1) ? t4 : 0u) +
+                                      ((mb & 2) ? t5 : 0u) + (m6 ? t6 : 0u) +
+                                      ((uint32_t)(beta + 1) << 12);
+                atomicAdd(&acc[slot], v1);
+              }
+            }
+      }
+      if (valid) {
+#pragma unroll
+        for (int m6 = 0; m6 < 2; ++m6)
+#pragma unroll
+          for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+            for (int m1 = 0; m1 < 2; ++m1) {
+              const uint32_t slot = ulane + (m1 ? t1 : 0u) + ((mb & 1) ? t4 : 0u) +
+                                    ((mb & 2) ? t5 : 0u) + (m6 ? t6 : 0u);
+              atomicAdd(&acc[slot], iacc[m6][mb][m1]);
+            }
+      }
+    }
+    __syncthreads();
+
+    for (int i = tid; i < NACC; i += THREADS) {
+      const uint32_t slot = mfma_slot((uint32_t)i);
+      const Acc v = acc[slot];
+      acc[slot] = Acc(0);
+      if constexpr (MODE == Out::Partial) {
+        static_cast<Acc*>(out)[(b_hi * n_shi + s_hi) * NACC + i] = v;
+      } else if constexpr (MODE == Out::CoefUniform) {
+        const int w = pauli_weight((uint64_t)i);
+        static_cast<double*>(out)[i] = acc_to_double(v) / (pow3d(n - w) * (double)shots);
+      } else if constexpr (MODE == Out::CoefPerBasis) {
+        const int w = pauli_weight((uint64_t)i);
+        static_cast<double*>(out)[i] = acc_to_double(v) / pow3d(n - w);
+      } else {
+        static_cast<int64_t*>(out)[i] = acc_to_i64(v);
+      }
+    }
+    __syncthreads();
+  }
+
+  uint32_t* __restrict__ rp = rowpart + (int64_t)blockIdx.x * NROWS;
+  for (int i = tid; i < NROWS; i += THREADS) rp[i] = rs_acc[i];
 }
 
 // ---------------------------------------------------------------------------------
@@ -546,7 +762,8 @@ __global__ __launch_bounds__(256) void rho_low_kernel(const double* __restrict__
                                                       void* __restrict__ out, int n) {
   constexpr int D = 1 << J;
   constexpr int NN = D * D;
-  __shared__ double re[NN], im[NN];  // [x][z], then [x][r]
+  constexpr int DP = D + 1;  // padded row stride (spreads the rows over LDS banks)
+  __shared__ double re[D * DP], im[D * DP];  // [x][z], then [x][r]
   const int64_t a_hi = blockIdx.x;
   const double* __restrict__ e = coef + a_hi * NN;
   for (int t = threadIdx.x; t < NN; t += 256) {
@@ -560,8 +777,8 @@ __global__ __launch_bounds__(256) void rho_low_kernel(const double* __restrict__
     }
     double vr = e[t], vi = 0.0;
     mul_neg_i_pow(ny, vr, vi);
-    re[x * D + z] = vr;
-    im[x * D + z] = vi;
+    re[x * DP + z] = vr;
+    im[x * DP + z] = vi;
   }
   __syncthreads();
 #pragma unroll 1
@@ -570,12 +787,12 @@ __global__ __launch_bounds__(256) void rho_low_kernel(const double* __restrict__
       const int x = t / (D / 2), k = t % (D / 2);
       const int lo = ((k >> bit) << (bit + 1)) | (k & ((1 << bit) - 1));
       const int hi = lo | (1 << bit);
-      const double a = re[x * D + lo], b = re[x * D + hi];
-      re[x * D + lo] = a + b;
-      re[x * D + hi] = a - b;
-      const double c = im[x * D + lo], f = im[x * D + hi];
-      im[x * D + lo] = c + f;
-      im[x * D + hi] = c - f;
+      const double a = re[x * DP + lo], b = re[x * DP + hi];
+      re[x * DP + lo] = a + b;
+      re[x * DP + hi] = a - b;
+      const double c = im[x * DP + lo], f = im[x * DP + hi];
+      im[x * DP + lo] = c + f;
+      im[x * DP + hi] = c - f;
     }
     __syncthreads();
   }
@@ -583,13 +800,13 @@ __global__ __launch_bounds__(256) void rho_low_kernel(const double* __restrict__
     const double scale = ldexp(1.0, -J);  // 2^-n with n == J
     for (int t = threadIdx.x; t < NN; t += 256) {
       const int r = t / D, c = t % D, x = r ^ c;
-      store_complex<OutT>(out, t, re[x * D + r] * scale, im[x * D + r] * scale);
+      store_complex<OutT>(out, t, re[x * DP + r] * scale, im[x * DP + r] * scale);
     }
   } else {
     double2* tmp = static_cast<double2*>(out) + a_hi * NN;
     for (int t = threadIdx.x; t < NN; t += 256) {
       const int r = t / D, x = t % D;
-      tmp[t] = make_double2(re[x * D + r], im[x * D + r]);
+      tmp[t] = make_double2(re[x * DP + r], im[x * DP + r]);
     }
   }
 }
@@ -599,9 +816,10 @@ __global__ __launch_bounds__(256) void rho_low_kernel(const double* __restrict__
 template <int XB, int HMAX, typename OutT>
 __global__ __launch_bounds__(256) void rho_high_kernel(const double2* __restrict__ tmp,
                                                        void* __restrict__ rho, int n, int J) {
-  __shared__ double re[XB << HMAX], im[XB << HMAX];  // [xo][z]
+  __shared__ double re[XB * ((1 << HMAX) + 1)], im[XB * ((1 << HMAX) + 1)];  // [xo][z], padded
   const int H = n - J;
   const int NH = 1 << H;
+  const int NHP = NH + 1;  // padded row stride
   const int D = 1 << J;
   int64_t bid = blockIdx.x;
   const int xblk = (int)(bid % (D / XB));
@@ -620,8 +838,8 @@ __global__ __launch_bounds__(256) void rho_high_kernel(const double2* __restrict
     const double2 v = tmp[(a_hi * D + r_lo) * D + x_lo];
     double vr = v.x, vi = v.y;
     mul_neg_i_pow(__popc((unsigned)(x_hi & z)), vr, vi);
-    re[xo * NH + z] = vr;
-    im[xo * NH + z] = vi;
+    re[xo * NHP + z] = vr;
+    im[xo * NHP + z] = vi;
   }
   __syncthreads();
   for (int bit = 0; bit < H; ++bit) {
@@ -629,12 +847,12 @@ __global__ __launch_bounds__(256) void rho_high_kernel(const double2* __restrict
       const int xo = t / (NH / 2), k = t % (NH / 2);
       const int lo = ((k >> bit) << (bit + 1)) | (k & ((1 << bit) - 1));
       const int hi = lo | (1 << bit);
-      const double a = re[xo * NH + lo], b = re[xo * NH + hi];
-      re[xo * NH + lo] = a + b;
-      re[xo * NH + hi] = a - b;
-      const double c = im[xo * NH + lo], f = im[xo * NH + hi];
-      im[xo * NH + lo] = c + f;
-      im[xo * NH + hi] = c - f;
+      const double a = re[xo * NHP + lo], b = re[xo * NHP + hi];
+      re[xo * NHP + lo] = a + b;
+      re[xo * NHP + hi] = a - b;
+      const double c = im[xo * NHP + lo], f = im[xo * NHP + hi];
+      im[xo * NHP + lo] = c + f;
+      im[xo * NHP + hi] = c - f;
     }
     __syncthreads();
   }
@@ -645,7 +863,7 @@ __global__ __launch_bounds__(256) void rho_high_kernel(const double2* __restrict
     const int x_lo = xblk * XB + xo;
     const int64_t row = ((int64_t)r_hi << J) | r_lo;
     const int64_t col = ((int64_t)(r_hi ^ x_hi) << J) | (r_lo ^ x_lo);
-    store_complex<OutT>(rho, row * dn + col, re[xo * NH + r_hi] * scale, im[xo * NH + r_hi] * scale);
+    store_complex<OutT>(rho, row * dn + col, re[xo * NHP + r_hi] * scale, im[xo * NHP + r_hi] * scale);
   }
 }
 

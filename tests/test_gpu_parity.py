@@ -213,3 +213,80 @@ def test_repeatable_and_linear():
     Tab = L.pauli_sums(_dev((a + b).astype(np.uint16)), 400)
     assert torch.equal(Ta, Ta2)
     assert torch.equal(Ta + Tb, Tab)
+
+
+# ---- int8-MFMA counts pass: same bars, and bit-identical to the plain kernel ----
+
+@pytest.mark.parametrize("n", [7, 8, 9, 10])
+def test_mfma_pauli_sums_bit_exact(n):
+    print(f"[mfma pauli_sums n={n}]", flush=True)
+    shots = 1000 if n < 9 else 300
+    counts = _haar_counts(n, shots, 80 + n)
+    c = _dev(counts)
+    T_m = L.pauli_sums(c, shots, flags=L.LRE_WHT_MFMA)
+    T_p = L.pauli_sums(c, shots)
+    assert torch.equal(T_m, T_p)
+    T_m = T_m.cpu().numpy()
+    if n <= 8:
+        np.testing.assert_array_equal(T_m, oracle.pauli_sums(n, counts))
+    else:
+        idx = np.random.default_rng(n).integers(0, 4 ** n, 2000)
+        np.testing.assert_array_equal(T_m[idx], oracle.pauli_sums(n, counts, idx))
+
+
+def test_mfma_full_uint16_range():
+    """Counts up to 65535 (both byte limbs used, binary64 partial sums): every row a
+    permutation of one vector, so all rows share one total."""
+    n = 7
+    rng = np.random.default_rng(90)
+    v = rng.integers(0, 65536, size=2 ** n).astype(np.uint16)
+    v[:4] = [65535, 65535, 0, 32768]
+    counts = np.stack([rng.permutation(v) for _ in range(3 ** n)])
+    shots = int(v.astype(np.int64).sum())
+    c = _dev(counts)
+    T_m = L.pauli_sums(c, shots, flags=L.LRE_WHT_MFMA)
+    assert torch.equal(T_m, L.pauli_sums(c, shots))
+    np.testing.assert_array_equal(T_m.cpu().numpy(), oracle.pauli_sums(n, counts))
+    coef, _ = L.estimate(c, shots, flags=L.LRE_WHT_MFMA | L.LRE_NO_RHO)
+    np.testing.assert_array_equal(coef.cpu().numpy(), oracle.coefs(n, counts, shots))
+
+
+@pytest.mark.parametrize("n", [7, 8])
+def test_mfma_estimate_uniform_bit_exact(n):
+    print(f"[mfma estimate uniform n={n}]", flush=True)
+    shots = 2000
+    counts = _haar_counts(n, shots, 100 + n)
+    coef, rho = L.estimate(_dev(counts), shots, flags=L.LRE_WHT_MFMA)
+    coef, rho = coef.cpu().numpy(), rho.cpu().numpy()
+    e_ref = oracle.coefs(n, counts, shots)
+    np.testing.assert_array_equal(coef, e_ref)
+    assert np.max(np.abs(rho - oracle.rho(n, e_ref))) <= TOL
+
+
+@pytest.mark.parametrize("n,nb_given", [(7, True), (8, False), (9, True)])
+def test_mfma_estimate_per_basis(n, nb_given):
+    print(f"[mfma estimate per-basis n={n}]", flush=True)
+    rng = np.random.default_rng(110 + n)
+    shots = rng.integers(100, 3000, size=3 ** n)
+    counts = ti.multinomial_counts(ti.born_probs_pure(n, ti.haar_state(n, rng)), shots, rng)
+    nb = _dev(counts.sum(axis=1).astype(np.int32)) if nb_given else None
+    coef, _ = L.estimate(_dev(counts), 0, n_per_basis=nb, flags=L.LRE_WHT_MFMA | L.LRE_NO_RHO)
+    coef = coef.cpu().numpy()
+    coef_p, _ = L.estimate(_dev(counts), 0, n_per_basis=nb, flags=L.LRE_NO_RHO)
+    assert np.max(np.abs(coef - coef_p.cpu().numpy())) <= TOL
+    if n <= 8:
+        assert np.max(np.abs(coef - oracle.coefs(n, counts, 0))) <= TOL
+    else:
+        idx = np.random.default_rng(n).integers(0, 4 ** n, 500)
+        assert np.max(np.abs(coef[idx] - oracle.coefs(n, counts, 0, idx=idx))) <= TOL
+    assert coef[0] == 1.0
+
+
+def test_mfma_error_flags():
+    counts = ti.maximally_mixed_counts(7, 2)
+    with pytest.raises(L.LreError) as e:
+        L.estimate(_dev(counts), 255, flags=L.LRE_WHT_MFMA)
+    assert e.value.status == L.LRE_E_SHOTS
+    coef, _ = L.estimate(_dev(counts), 256, flags=L.LRE_WHT_MFMA)
+    c = coef.cpu().numpy()
+    assert c[0] == 1.0 and np.all(c[1:] == 0.0)
