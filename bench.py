@@ -188,7 +188,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="n14", choices=["n14", "n12", "n8"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--wht", default="mfma", choices=["mfma", "plain"],
+    ap.add_argument("--wht", default="plain", choices=["mfma", "plain"],
                     help="counts-pass Walsh transform for the headline run; the other one is "
                          "timed too for the MFMA-vs-plain ratio")
     args = ap.parse_args()
@@ -270,7 +270,7 @@ def main():
                    "wht": "int8-mfma" if head_flags else "plain-int32", "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "fold_counts_kernel (counts pass of step (i))",
+                     "kernel": "fold_counts_stream_kernel (counts pass of step (i))",
                      "algorithmic_bytes_per_launch": 2.0 * n_counts},
         "end_to_end_s": ms_step / 1e3,
         "step_ms": {"counts_pass": t_pass1 * 1e3, "step_i": sum(step_i) / len(step_i),

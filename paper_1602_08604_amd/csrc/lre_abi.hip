@@ -137,35 +137,68 @@ struct Fold1Args {
   hipStream_t st;
 };
 
-constexpr int kRegDigits = 2;  // basis digits folded in registers by the counts pass
+// Counts-pass block: one row group per tile row-set, i.e. NRS * LPC threads (3^Q rows
+// of 2^Q outcomes), split in three for Q = 7 (81 row-sets of 16 lanes -> 432 threads,
+// each group walks three row-sets).
+template <int Q>
+constexpr int fold1_threads() {
+  constexpr int t = StreamGeom<Q>::NRS * StreamGeom<Q>::LPC;
+  return t > 1024 ? t / 3 : (t < 64 ? 64 : t);
+}
 
-template <int Q, typename Acc, bool PB, Out M>
+// Waves per SIMD the compiler must leave room for: two blocks per CU when two
+// accumulator tiles fit in LDS (32-bit accumulators), else no constraint.
+template <int Q, typename Acc>
+constexpr int fold1_minwaves() {
+  constexpr int waves = (fold1_threads<Q>() + 63) / 64;
+  constexpr long lds = (long)StreamGeom<Q>::NACC * (long)sizeof(Acc) + 4L * StreamGeom<Q>::NROWS;
+  return (Q == 7 && 2 * lds <= 160L * 1024) ? (2 * waves + 3) / 4 : 1;
+}
+
+template <int Q, typename Acc, bool PB, Out M, bool MAD24>
 void launch_fold1(const Fold1Args& a) {
-  constexpr int TH = Q == 7 ? 512 : 256;
-  hipLaunchKernelGGL((fold_counts_kernel<Q, TH, kRegDigits, Acc, PB, M>), dim3((unsigned)a.blocks), dim3(TH), 0,
+  constexpr int TH = fold1_threads<Q>();
+  static_assert(TH <= 1024 && (TH % StreamGeom<Q>::LPC) == 0, "counts-pass block shape");
+  hipLaunchKernelGGL((fold_counts_stream_kernel<Q, TH, Acc, PB, M, MAD24, fold1_minwaves<Q, Acc>()>), dim3((unsigned)a.blocks), dim3(TH), 0,
                      a.st, a.counts, a.n, a.chunks, a.nb, a.out, a.rowpart, a.shots);
 }
+
+// The lane butterflies of 32-bit sums use a 24-bit multiply-add when every value they
+// see is below 2^23 in magnitude: values are bounded by the counts of the 3^3 rows a
+// lane group walks, i.e. by 27 * shots for valid data (rows that exceed `shots` are
+// flagged by the row check, so wrong values then never reach the caller as a result).
+bool fold1_mad24(uint64_t shots) { return shots > 0 && 27ull * shots < (1ull << 23); }
 
 template <int Q>
 bool fold1_q(Ty t, bool pb, Out m, const Fold1Args& a) {
   if (pb) {
-    if (m == Out::Partial) launch_fold1<Q, double, true, Out::Partial>(a);
-    else if (m == Out::CoefPerBasis) launch_fold1<Q, double, true, Out::CoefPerBasis>(a);
+    if (m == Out::Partial) launch_fold1<Q, double, true, Out::Partial, false>(a);
+    else if (m == Out::CoefPerBasis) launch_fold1<Q, double, true, Out::CoefPerBasis, false>(a);
     else return false;
     return true;
   }
   if (t == Ty::U32) {
+    const bool m24 = fold1_mad24(a.shots);
     switch (m) {
-      case Out::Partial: launch_fold1<Q, uint32_t, false, Out::Partial>(a); return true;
-      case Out::CoefUniform: launch_fold1<Q, uint32_t, false, Out::CoefUniform>(a); return true;
-      case Out::PauliT: launch_fold1<Q, uint32_t, false, Out::PauliT>(a); return true;
+      case Out::Partial:
+        m24 ? launch_fold1<Q, uint32_t, false, Out::Partial, true>(a)
+            : launch_fold1<Q, uint32_t, false, Out::Partial, false>(a);
+        return true;
+      case Out::CoefUniform:
+        m24 ? launch_fold1<Q, uint32_t, false, Out::CoefUniform, true>(a)
+            : launch_fold1<Q, uint32_t, false, Out::CoefUniform, false>(a);
+        return true;
+      case Out::PauliT:
+        m24 ? launch_fold1<Q, uint32_t, false, Out::PauliT, true>(a)
+            : launch_fold1<Q, uint32_t, false, Out::PauliT, false>(a);
+        return true;
       default: return false;
     }
   }
   switch (m) {
-    case Out::Partial: launch_fold1<Q, double, false, Out::Partial>(a); return true;
-    case Out::CoefUniform: launch_fold1<Q, double, false, Out::CoefUniform>(a); return true;
-    case Out::PauliT: launch_fold1<Q, double, false, Out::PauliT>(a); return true;
+    case Out::Partial: launch_fold1<Q, double, false, Out::Partial, false>(a); return true;
+    case Out::CoefUniform: launch_fold1<Q, double, false, Out::CoefUniform, false>(a); return true;
+    case Out::PauliT: launch_fold1<Q, double, false, Out::PauliT, false>(a); return true;
     default: return false;
   }
 }

@@ -177,33 +177,15 @@ __device__ __forceinline__ void wht_lanes(int32_t* x, int lam) {
 }
 
 // ---------------------------------------------------------------------------------
-// Pass 1: counts -> partials (or the final coefficients when Q == n).
+// Row tiles of the counts: 2^Q consecutive outcomes of a row, V per lane.
 
-template <int Q, int RDMAX = 2>
+template <int Q>
 struct Fold1Geom {
   static constexpr int V = Q >= 3 ? 8 : (1 << Q);  // outcomes per lane
   static constexpr int LB = ilog2c(V);              // Walsh bits held in registers
   static constexpr int LPC = (1 << Q) / V;          // lanes per tile row
   static constexpr int LL = Q - LB;                 // Walsh bits across lanes
-  static constexpr int RD = LB >= RDMAX ? RDMAX : LB;  // basis digits folded in registers
-  static constexpr int R = (int)ipow3(RD);          // rows per lane
-  static constexpr int NAR = (int)ipow4(RD);        // register-folded letters
-  static constexpr int VH = V >> RD;                // Walsh values per lane per letter
-  static constexpr int RS = (int)ipow3(Q - RD);     // row-sets per tile
-  static constexpr int NACC = (int)ipow4(Q);        // accumulators per tile
-  static constexpr int NROWS = (int)ipow3(Q);       // rows per tile
 };
-
-// LDS slot of Pauli index a (Q base-4 digits) in the counts-pass accumulator:
-// [letters of positions < RD][positions RD..LB-1][positions LB..Q-1], most significant
-// first, i.e. the three digit fields of a in reverse order.
-template <int Q, int RD, int LB>
-__device__ __forceinline__ uint32_t acc_slot(uint32_t a) {
-  const uint32_t ar = a & ((1u << (2 * RD)) - 1);
-  const uint32_t ureg = (a >> (2 * RD)) & ((1u << (2 * (LB - RD))) - 1);
-  const uint32_t ulane = a >> (2 * LB);
-  return (ar << (2 * (Q - RD))) | (ureg << (2 * (Q - LB))) | ulane;
-}
 
 template <int V>
 __device__ __forceinline__ void load_counts(const uint16_t* __restrict__ p, int32_t* x) {
@@ -220,6 +202,25 @@ __device__ __forceinline__ void load_counts(const uint16_t* __restrict__ p, int3
     uint32_t w = *reinterpret_cast<const uint32_t*>(p);
     x[0] = (int32_t)(w & 0xffffu); x[1] = (int32_t)(w >> 16);
   }
+}
+
+template <int V>
+__device__ __forceinline__ void load_raw(const uint16_t* __restrict__ p, uint32_t* w) {
+  if constexpr (V == 8) {
+    const uint4 u = *reinterpret_cast<const uint4*>(p);
+    w[0] = u.x; w[1] = u.y; w[2] = u.z; w[3] = u.w;
+  } else if constexpr (V == 4) {
+    const uint2 u = *reinterpret_cast<const uint2*>(p);
+    w[0] = u.x; w[1] = u.y;
+  } else {
+    w[0] = *reinterpret_cast<const uint32_t*>(p);
+  }
+}
+
+template <int V>
+__device__ __forceinline__ void unpack_raw(const uint32_t* w, int32_t* x) {
+#pragma unroll
+  for (int k = 0; k < V / 2; ++k) { x[2 * k] = (int32_t)(w[k] & 0xffffu); x[2 * k + 1] = (int32_t)(w[k] >> 16); }
 }
 
 // Accumulator conversion of an exact chunk sum.
@@ -241,18 +242,126 @@ __device__ __forceinline__ int64_t acc_to_i64(Acc v) {
   else return (int64_t)v;
 }
 
-// counts : [3^n][2^n] uint16.  Block -> (b_hi, run of `chunks` consecutive s_hi).
-// out    : Partial: Acc [3^{n-Q}][2^{n-Q}][4^Q]; CoefUniform / CoefPerBasis: double
-//          [4^n]; PauliT: int64 [4^n]  (the final modes require Q == n).
-// rowpart: uint32 [3^{n-Q}][runs][3^Q]: the block's partial row sums (runs = blocks
-//          per row group); check_rows_kernel adds the runs and checks the totals.
-// nb     : per-basis totals (PER_BASIS only).
-template <int Q, int THREADS, int RDMAX, typename Acc, bool PER_BASIS, Out MODE>
-__global__ __launch_bounds__(THREADS) void fold_counts_kernel(
+// ---------------------------------------------------------------------------------
+// Pass 1 (counts pass): counts -> partials (or the final coefficients when Q == n).
+// A block tile is 3^Q rows x 2^Q consecutive outcomes (V = 8 outcomes per lane, LPC
+// lanes per tile row).  The per-qubit maps act on different qubits and commute, so
+// they are applied in the order that keeps most of the work in registers:
+//   1. each lane walks the 3^LB rows that differ in the basis digits of the LB qubits
+//      whose outcome bits it holds in registers, doing the in-register butterflies and
+//      folding those LB qubits completely with a mixed-radix cascade of accumulators
+//      (level k holds the identity-letter sums of qubit k);
+//   2. only the 4^LB values that leave the cascade ("emissions", one per letter
+//      combination of those qubits) get the lane butterflies (DPP) of the remaining
+//      LL = Q - LB outcome bits and are added into the LDS accumulator, whose atomics
+//      fold the last LL qubits over the row-sets.
+// Per 27 rows x 8 outcomes a lane issues 64 emissions: 0.30 LDS atomics per count and
+// the DPP work runs on 30% of the values.
+
+// One DPP butterfly stage on a 32-bit integer value: lower member x + partner, upper
+// partner - x.  MAD24: |x| < 2^23 is guaranteed by the caller (v_mad_i32_i24);
+// otherwise an exact negate-and-add.
+template <int CTRL, bool MAD24>
+__device__ __forceinline__ void lane_bfly(int32_t& x, int32_t sgn) {
+  const int32_t p = __builtin_amdgcn_mov_dpp(x, CTRL, 0xF, 0xF, true);
+  if constexpr (MAD24) {
+    x = __mul24(x, sgn) + p;
+  } else {
+    const int32_t neg = sgn >> 31;           // -1 for the upper member, 0 otherwise
+    x = p + ((x ^ neg) - neg);
+  }
+}
+
+template <int CTRL, bool MAD24>
+__device__ __forceinline__ void lane_bfly(uint32_t& x, int32_t sgn) {
+  int32_t v = (int32_t)x;
+  lane_bfly<CTRL, MAD24>(v, sgn);
+  x = (uint32_t)v;
+}
+
+template <int CTRL, bool MAD24>
+__device__ __forceinline__ void lane_bfly(double& x, int32_t sgn) {
+  const uint64_t u = __double_as_longlong(x);
+  const int32_t lo = __builtin_amdgcn_mov_dpp((int32_t)(uint32_t)u, CTRL, 0xF, 0xF, true);
+  const int32_t hi = __builtin_amdgcn_mov_dpp((int32_t)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, true);
+  const double p = __longlong_as_double(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+  x = fma(x, (double)sgn, p);                // exact: sgn = +-1
+}
+
+// Per-lane signs of the NL lane stages (see wht_lanes for directions and masks).
+template <int NL>
+__device__ __forceinline__ void lane_signs(int lam, int32_t* sg) {
+  constexpr int um[4][4] = {{1, 0, 0, 0}, {1, 2, 0, 0}, {4, 5, 6, 0}, {8, 12, 5, 6}};
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    sg[k] = (__popc((unsigned)(lam & um[NL > 0 ? NL - 1 : 0][k])) & 1) ? -1 : 1;
+    asm volatile("" : "+v"(sg[k]));          // keep the +-1 range opaque (see lane_stage)
+  }
+}
+
+template <int NL, bool MAD24, typename T>
+__device__ __forceinline__ void wht_lanes1(T& x, const int32_t* sg) {
+  if constexpr (NL == 1) {
+    lane_bfly<kDppQuadXor1, MAD24>(x, sg[0]);
+  } else if constexpr (NL == 2) {
+    lane_bfly<kDppQuadXor1, MAD24>(x, sg[0]);
+    lane_bfly<kDppQuadXor2, MAD24>(x, sg[1]);
+  } else if constexpr (NL == 3) {
+    lane_bfly<kDppHalfMirror, MAD24>(x, sg[0]);
+    lane_bfly<kDppQuadXor1, MAD24>(x, sg[1]);
+    lane_bfly<kDppQuadXor2, MAD24>(x, sg[2]);
+  } else if constexpr (NL == 4) {
+    lane_bfly<kDppMirror, MAD24>(x, sg[0]);
+    lane_bfly<kDppHalfMirror, MAD24>(x, sg[1]);
+    lane_bfly<kDppQuadXor1, MAD24>(x, sg[2]);
+    lane_bfly<kDppQuadXor2, MAD24>(x, sg[3]);
+  }
+}
+
+// Sum of a 32-bit value over the 2^NL lanes of a row group (result valid in every lane).
+template <int NL>
+__device__ __forceinline__ uint32_t lane_sum(uint32_t x) {
+  if constexpr (NL >= 4) x += (uint32_t)__builtin_amdgcn_mov_dpp((int)x, kDppMirror, 0xF, 0xF, true);
+  if constexpr (NL >= 3) x += (uint32_t)__builtin_amdgcn_mov_dpp((int)x, kDppHalfMirror, 0xF, 0xF, true);
+  if constexpr (NL >= 2) x += (uint32_t)__builtin_amdgcn_mov_dpp((int)x, kDppQuadXor2, 0xF, 0xF, true);
+  if constexpr (NL >= 1) x += (uint32_t)__builtin_amdgcn_mov_dpp((int)x, kDppQuadXor1, 0xF, 0xF, true);
+  return x;
+}
+
+template <int Q>
+struct StreamGeom {
+  static constexpr int V = Q >= 3 ? 8 : (1 << Q);  // outcomes per lane
+  static constexpr int LB = ilog2c(V);              // qubits folded in registers
+  static constexpr int LPC = (1 << Q) / V;          // lanes per tile row
+  static constexpr int LL = Q - LB;                 // outcome bits across lanes
+  static constexpr int NSEQ = (int)ipow3(LB);       // rows walked by one lane group
+  static constexpr int NRS = (int)ipow3(Q - LB);    // row-sets (walks) per tile
+  static constexpr int NACC = (int)ipow4(Q);
+  static constexpr int NROWS = (int)ipow3(Q);
+};
+
+// LDS slot of Pauli index a: [letters of the LB register qubits][letters of the lane
+// qubits], the lane letters XOR-swizzled by the register letters.  An emission (one
+// register-letter code for the whole wave, lane letters differing) and the write-out
+// (consecutive a, i.e. consecutive register letters) both spread over the banks.
+template <int Q, int LB>
+__device__ __forceinline__ uint32_t stream_slot_of(uint32_t areg, uint32_t alane) {
+  constexpr uint32_t hmask = (1u << (2 * (Q - LB))) - 1;
+  return (areg << (2 * (Q - LB))) | (alane ^ (areg & hmask));
+}
+
+template <int Q, int LB>
+__device__ __forceinline__ uint32_t stream_slot(uint32_t a) {
+  return stream_slot_of<Q, LB>(a & ((1u << (2 * LB)) - 1), a >> (2 * LB));
+}
+
+template <int Q, int THREADS, typename Acc, bool PER_BASIS, Out MODE, bool MAD24, int MINWAVES = 1>
+__global__ __launch_bounds__(THREADS, MINWAVES) void fold_counts_stream_kernel(
     const uint16_t* __restrict__ counts, int n, int chunks, const uint32_t* __restrict__ nb,
     void* __restrict__ out, uint32_t* __restrict__ rowpart, uint64_t shots) {
-  using G = Fold1Geom<Q, RDMAX>;
+  using G = StreamGeom<Q>;
   constexpr int GROUPS = THREADS / G::LPC;
+  constexpr int LB = G::LB;
   __shared__ Acc acc[G::NACC];
   __shared__ uint32_t rs_acc[G::NROWS];
 
@@ -265,92 +374,139 @@ __global__ __launch_bounds__(THREADS) void fold_counts_kernel(
   const int64_t row0 = b_hi * G::NROWS;
   const int64_t rowlen = (int64_t)1 << n;
 
+  int32_t sg[G::LL > 0 ? G::LL : 1];
+  lane_signs<G::LL>(lam, sg);
+  const int lw = lane_walsh<G::LL>(lam);
+
   for (int i = tid; i < G::NACC; i += THREADS) acc[i] = Acc(0);
   for (int i = tid; i < G::NROWS; i += THREADS) rs_acc[i] = 0;
   __syncthreads();
 
   for (int c = 0; c < chunks; ++c) {
     const int64_t s_hi = s_hi0 + c;
-    for (int rs = grp; rs < G::RS; rs += GROUPS) {
-      const int64_t rowb = row0 + (int64_t)rs * G::R;
-      int32_t x[G::R][G::V];
-#pragma unroll
-      for (int beta = 0; beta < G::R; ++beta)
-        load_counts<G::V>(counts + (rowb + beta) * rowlen + (s_hi << Q) + lam * G::V, x[beta]);
-
-#pragma unroll
-      for (int beta = 0; beta < G::R; ++beta) {
-        wht_regs<G::LB>(x[beta]);
-        wht_lanes<G::LL, G::V>(x[beta], lam);
-      }
-      if (lam == 0) {
-#pragma unroll
-        for (int beta = 0; beta < G::R; ++beta) atomicAdd(&rs_acc[rs * G::R + beta], (uint32_t)x[beta][0]);
-      }
-
-      // Fold the RD lowest qubits in registers: o[vh][ar] sums, over the rows beta of
-      // the row-set compatible with letters ar, the Walsh value whose low RD bits
-      // select the non-identity letters.  Per-basis mode divides each row by N_b first.
-      Acc o[G::VH][G::NAR];
-#pragma unroll
-      for (int vh = 0; vh < G::VH; ++vh)
-#pragma unroll
-        for (int ar = 0; ar < G::NAR; ++ar) o[vh][ar] = Acc(0);
-      StaticFor<0, G::R>::run([&](auto bc) __attribute__((always_inline)) {
-        constexpr int beta = decltype(bc)::value;
-        Acc y[G::V];
-        if constexpr (PER_BASIS) {
-          const uint32_t N = nb[rowb + beta];
-          const double inv = N ? 1.0 / (double)N : 0.0;  // empty basis: flagged by the row check
-#pragma unroll
-          for (int v = 0; v < G::V; ++v) y[v] = (double)x[beta][v] * inv;
-        } else {
-#pragma unroll
-          for (int v = 0; v < G::V; ++v) y[v] = to_acc<Acc>(x[beta][v]);
-        }
-        StaticFor<0, G::NAR>::run([&](auto ac) __attribute__((always_inline)) {
-          constexpr int ar = decltype(ac)::value;
-          if constexpr (compat(beta, ar, G::RD)) {
-            constexpr int ml = mlo_of(ar, G::RD);
-#pragma unroll
-            for (int vh = 0; vh < G::VH; ++vh) o[vh][ar] += y[(vh << G::RD) | ml];
-          }
-        });
-      });
-
-      // Accumulator slot.  Positions >= RD get the letter (b_p + 1) where Walsh bit p is
-      // set, I otherwise; Walsh bits RD..LB-1 are register bits (vh), bits LB..Q-1 come
-      // from the lane (relabelled by lane_walsh).  LDS layout (acc_slot): the lane-owned
-      // letters occupy the low bits so that the lanes of one atomic spread over banks.
-      const int lw = lane_walsh<G::LL>(lam);
+    for (int rs = grp; rs < G::NRS; rs += GROUPS) {
+      // Letters of the lane qubits for this lane's (relabelled) Walsh index: slot low bits.
       uint32_t ulane = 0;
-      uint32_t treg[G::LB - G::RD > 0 ? G::LB - G::RD : 1] = {};
       {
         int t = rs;
-        StaticFor<0, Q - G::RD>::run([&](auto jc) __attribute__((always_inline)) {
-          constexpr int j = decltype(jc)::value;
-          constexpr int p = G::RD + j;
-          const uint32_t dgt = (uint32_t)(t % 3 + 1);
+#pragma unroll
+        for (int j = 0; j < G::LL; ++j) {
+          if ((lw >> j) & 1) ulane += (uint32_t)(t % 3 + 1) << (2 * j);
           t /= 3;
-          if constexpr (p < G::LB) treg[j] = dgt << (2 * (Q - G::LB + j));
-          else if ((lw >> (p - G::LB)) & 1) ulane += dgt << (2 * (p - G::LB));
-        });
+        }
       }
+      const int64_t rowb = row0 + (int64_t)rs * G::NSEQ;
+      const uint16_t* __restrict__ cbase = counts + rowb * rowlen + (s_hi << Q) + lam * G::V;
+
+      // Emission of a value whose register-qubit letters are `areg` (4^LB code).
+      auto emit = [&](Acc v, uint32_t areg) __attribute__((always_inline)) {
+        wht_lanes1<G::LL, MAD24>(v, sg);
+        atomicAdd(&acc[stream_slot_of<Q, LB>(areg, ulane)], v);
+      };
+
+      if constexpr (LB == 3) {
+        Acc L1[4][2], L2[4][4];
 #pragma unroll
-      for (int vh = 0; vh < G::VH; ++vh) {
-        uint32_t off = ulane;
+        for (int a = 0; a < 4; ++a) { L1[a][0] = L1[a][1] = Acc(0); L2[a][0] = L2[a][1] = L2[a][2] = L2[a][3] = Acc(0); }
+#pragma unroll 1
+        for (int d2 = 0; d2 < 3; ++d2) {
+          uint32_t raw[9][4];
 #pragma unroll
-        for (int q = 0; q < G::LB - G::RD; ++q)
-          if ((vh >> q) & 1) off += treg[q];
+          for (int r = 0; r < 9; ++r) load_raw<8>(cbase + (int64_t)(9 * d2 + r) * rowlen, raw[r]);
+          StaticFor<0, 3>::run([&](auto d1c) __attribute__((always_inline)) {
+            constexpr int d1 = decltype(d1c)::value;
+            Acc L0[4] = {Acc(0), Acc(0), Acc(0), Acc(0)};
+            StaticFor<0, 3>::run([&](auto d0c) __attribute__((always_inline)) {
+              constexpr int d0 = decltype(d0c)::value;
+              constexpr int r = 3 * d1 + d0;
+              int32_t x[8];
+              unpack_raw<8>(raw[r], x);
+              wht_regs<3>(x);
+              const uint32_t tot = lane_sum<G::LL>((uint32_t)x[0]);
+              if (lam == 0) atomicAdd(&rs_acc[rs * G::NSEQ + 9 * d2 + r], tot);
+              Acc y[8];
+              if constexpr (PER_BASIS) {
+                const uint32_t N = nb[rowb + 9 * d2 + r];
+                const double inv = N ? 1.0 / (double)N : 0.0;  // empty basis: flagged by the row check
 #pragma unroll
-        for (int ar = 0; ar < G::NAR; ++ar)
-          atomicAdd(&acc[off + ((uint32_t)ar << (2 * (Q - G::RD)))], o[vh][ar]);
+                for (int v = 0; v < 8; ++v) y[v] = (double)x[v] * inv;
+              } else {
+#pragma unroll
+                for (int v = 0; v < 8; ++v) y[v] = to_acc<Acc>(x[v]);
+              }
+              // y[v], v = m0 + 2 m1 + 4 m2.  Qubit 0: m0 = 0 -> identity (L0); m0 = 1 -> letter d0+1.
+#pragma unroll
+              for (int mr = 0; mr < 4; ++mr) {
+                L0[mr] += y[2 * mr];
+                const Acc w = y[2 * mr + 1];
+                const int m1 = mr & 1, m2 = mr >> 1;
+                if (m1 == 0) {
+                  L1[d0 + 1][m2] += w;
+                } else if (m2 == 0) {
+                  L2[d0 + 1][d1 + 1] += w;
+                } else {
+                  emit(w, (uint32_t)((d0 + 1) + 4 * (d1 + 1) + 16 * (d2 + 1)));
+                }
+              }
+            });
+            // End of the qubit-0 walk: its identity sums move up (letter I at qubit 0).
+#pragma unroll
+            for (int mr = 0; mr < 4; ++mr) {
+              const int m1 = mr & 1, m2 = mr >> 1;
+              if (m1 == 0) L1[0][m2] += L0[mr];
+              else if (m2 == 0) L2[0][d1 + 1] += L0[mr];
+              else emit(L0[mr], (uint32_t)(4 * (d1 + 1) + 16 * (d2 + 1)));
+            }
+          });
+          // End of the qubit-1 walk (letters of qubit 1 now final).
+#pragma unroll
+          for (int a0 = 0; a0 < 4; ++a0) {
+            L2[a0][0] += L1[a0][0];
+            emit(L1[a0][1], (uint32_t)(a0 + 16 * (d2 + 1)));
+            L1[a0][0] = L1[a0][1] = Acc(0);
+          }
+        }
+        // End of the qubit-2 walk: identity letter at qubit 2.
+#pragma unroll
+        for (int a0 = 0; a0 < 4; ++a0)
+#pragma unroll
+          for (int a1 = 0; a1 < 4; ++a1) emit(L2[a0][a1], (uint32_t)(a0 + 4 * a1));
+      } else {
+        // Small tiles (Q < 3): one lane holds a whole row (LPC = 1); plain direct fold.
+        static_assert(G::LPC == 1, "small-tile path expects one lane per row");
+        for (int r = 0; r < G::NSEQ; ++r) {
+          uint32_t raw[G::V / 2];
+          load_raw<G::V>(cbase + (int64_t)r * rowlen, raw);
+          int32_t x[G::V];
+          unpack_raw<G::V>(raw, x);
+          wht_regs<LB>(x);
+          atomicAdd(&rs_acc[rs * G::NSEQ + r], (uint32_t)x[0]);
+          double inv = 1.0;
+          if constexpr (PER_BASIS) {
+            const uint32_t N = nb[rowb + r];
+            inv = N ? 1.0 / (double)N : 0.0;
+          }
+#pragma unroll
+          for (int m = 0; m < G::V; ++m) {
+            uint32_t areg = 0;
+            int t = r;
+#pragma unroll
+            for (int k = 0; k < LB; ++k) {
+              if ((m >> k) & 1) areg += (uint32_t)(t % 3 + 1) << (2 * k);
+              t /= 3;
+            }
+            Acc v;
+            if constexpr (PER_BASIS) v = (double)x[m] * inv;
+            else v = to_acc<Acc>(x[m]);
+            atomicAdd(&acc[stream_slot_of<Q, LB>(areg, 0)], v);
+          }
+        }
       }
     }
     __syncthreads();
 
     for (int i = tid; i < G::NACC; i += THREADS) {
-      const uint32_t slot = acc_slot<Q, G::RD, G::LB>((uint32_t)i);
+      const uint32_t slot = stream_slot<Q, LB>((uint32_t)i);
       const Acc v = acc[slot];
       acc[slot] = Acc(0);
       if constexpr (MODE == Out::Partial) {

@@ -80,7 +80,9 @@ def test_estimate_per_basis(n, nb_given):
     coef, rho = coef.cpu().numpy(), rho.cpu().numpy()
     e_ref = oracle.coefs(n, counts, 0)
     assert np.max(np.abs(coef - e_ref)) <= TOL
-    assert coef[0] == 1.0
+    # Frequencies c/N_b are formed with the rounded reciprocal of N_b, so the trace
+    # coefficient is 1 only up to rounding (the oracle's is exactly 1).
+    assert abs(coef[0] - 1.0) <= TOL
     assert np.max(np.abs(rho - oracle.rho(n, e_ref))) <= TOL
     assert np.array_equal(rho, rho.conj().T)
 
@@ -279,7 +281,7 @@ def test_mfma_estimate_per_basis(n, nb_given):
     else:
         idx = np.random.default_rng(n).integers(0, 4 ** n, 500)
         assert np.max(np.abs(coef[idx] - oracle.coefs(n, counts, 0, idx=idx))) <= TOL
-    assert coef[0] == 1.0
+    assert abs(coef[0] - 1.0) <= TOL    # rounded reciprocal of N_b: trace 1 up to rounding
 
 
 def test_mfma_error_flags():
