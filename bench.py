@@ -17,7 +17,6 @@ from __future__ import annotations
 
 import argparse
 import ctypes
-import hashlib
 import json
 import math
 import os
@@ -72,14 +71,6 @@ class StageEvents:
                 self.hip.hipEventDestroy(ctypes.c_void_p(e))
 
 
-def kernel_source_hash():
-    h = hashlib.sha256()
-    for rel in ("paper_1602_08604_amd/csrc/lre_kernels.hpp", "paper_1602_08604_amd/csrc/lre_abi.hip"):
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()[:16]
-
-
 def measured_traffic(workload):
     """HBM bytes per counts-pass launch from the committed rocprofv3 PMC summary, if it was
     taken on the current kernel source; else None."""
@@ -88,6 +79,7 @@ def measured_traffic(workload):
         return None
     with open(path) as f:
         rec = json.load(f)
+    from paper_1602_08604_amd.profsum import kernel_source_hash
     if rec.get("kernel_source_hash") != kernel_source_hash():
         return None
     return rec.get("hbm_bytes_per_launch")
@@ -188,6 +180,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="n14", choices=["n14", "n12", "n8"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="time only the headline Walsh path (no MFMA-vs-plain ratio)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed steps, run one plain 1 GiB copy kernel (negation of a "
+                         "float32 tensor) as the reference for rocprofv3 byte counters")
     ap.add_argument("--wht", default="plain", choices=["mfma", "plain"],
                     help="counts-pass Walsh transform for the headline run; the other one is "
                          "timed too for the MFMA-vs-plain ratio")
@@ -244,7 +241,13 @@ def main():
     mfma_ok = n >= 7
     head_flags = lre.LRE_WHT_MFMA if (args.wht == "mfma" and mfma_ok) else 0
     head = timed(head_flags)
-    other = timed(0 if head_flags else lre.LRE_WHT_MFMA) if mfma_ok else None
+    other = timed(0 if head_flags else lre.LRE_WHT_MFMA) if (mfma_ok and not args.no_compare) else None
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     ms_step = head["ms_step"]
     pass1, step_i, step_ii = head["pass1"], head["step_i"], head["step_ii"]
 
