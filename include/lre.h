@@ -54,7 +54,8 @@ typedef enum {
   LRE_E_HIP = 3,          /* a HIP runtime call failed */
   LRE_E_SHOTS = 4,        /* a basis row does not sum to its declared total */
   LRE_E_EMPTY_BASIS = 5,  /* per-basis mode: a basis with zero counts */
-  LRE_E_UNSUPPORTED = 6   /* valid request that this build cannot serve */
+  LRE_E_UNSUPPORTED = 6,  /* valid request that this build cannot serve */
+  LRE_E_TIMEOUT = 7       /* a batched run's bounded wait for a dependency expired */
 } lre_status;
 
 #define LRE_MAX_QUBITS 14
@@ -103,7 +104,7 @@ lre_status lre_estimate(lre_ctx* ctx, int n, const uint16_t* counts, uint64_t sh
                         size_t workspace_bytes, uint32_t flags, void* stream);
 
 /* Synchronise `stream`, read and clear the context's device flag word.  Returns
- * LRE_E_SHOTS, LRE_E_EMPTY_BASIS, LRE_E_HIP or LRE_OK. */
+ * LRE_E_SHOTS, LRE_E_EMPTY_BASIS, LRE_E_TIMEOUT, LRE_E_HIP or LRE_OK. */
 lre_status lre_check(lre_ctx* ctx, void* stream);
 
 /* Profiling hook.  events: `count` (<= 4) caller-created hipEvent_t handles, or NULL to
@@ -131,6 +132,81 @@ lre_status lre_pauli_sums(lre_ctx* ctx, int n, const uint16_t* counts, uint64_t 
  *   out   : device int32 [num_bases][2^n]. */
 lre_status lre_signed_sums(lre_ctx* ctx, int n, const uint16_t* counts, const int64_t* bases,
                            int64_t num_bases, int32_t* out, uint32_t flags, void* stream);
+
+/* ---------------------------------------------------------------------------------
+ * Batched estimation: many independent instances (each its own n, counts and shots)
+ * in one launch of a persistent kernel.  Every instance gets exactly what
+ * lre_estimate returns for it (steps (i) and (ii), Sec. II eqs. 3-4): the same
+ * kernels' arithmetic, bit-identical coefficients and rho.
+ *
+ * lre_batch_plan builds a work list (the counts-pass tiles, later passes, row checks
+ * and step-(ii) blocks of every instance, in dependency order, split into work items)
+ * and uploads it.  lre_batch_run enqueues two kernels: a fill kernel that clears the
+ * item and dependency counters in the workspace, then one persistent kernel whose
+ * workgroups take items from the list in order; an item that needs the results of
+ * earlier items waits for their counters (a bounded wait: on expiry the item is
+ * skipped and LRE_E_TIMEOUT is raised through lre_check).  lre_batch_run makes no
+ * allocation, copy or memset and may be captured into a HIP graph.
+ */
+#define LRE_BATCH_MAX_QUBITS 9
+
+typedef struct {
+  int n;                   /* 1 <= n <= LRE_BATCH_MAX_QUBITS */
+  const uint16_t* counts;  /* device uint16 [3^n][2^n], 16-byte aligned */
+  uint64_t shots;          /* per-basis total, > 0, with 3^n * shots < 2^31 (checked per
+                              basis like lre_estimate; per-basis totals are not
+                              supported in a batch: LRE_E_UNSUPPORTED) */
+  double* coef;            /* device double [4^n], 8-byte aligned */
+  void* rho;               /* device complex [2^n][2^n], 16-byte aligned; unused with
+                              LRE_NO_RHO */
+} lre_instance;
+
+/* Work-item shape of a plan (what lre_batch_tune chooses between). */
+typedef struct {
+  int workers_per_cu;   /* persistent workgroups per compute unit: 1 or 2 */
+  int counts_tiles;     /* counts-pass tiles (3^7 rows x 128 outcomes) per item, >= 1 */
+  int fold_cols;        /* later-pass columns per item, multiple of 432 */
+  int rho_blocks;       /* step-(ii) blocks per item, >= 1 */
+  int interleave;       /* 0: stage by stage, largest instances first;
+                           1: instance by instance (all stages of an instance together) */
+} lre_batch_tiles;
+
+typedef struct lre_batch lre_batch;
+
+/* Plan a batch of `count` instances (count >= 1).  flags: LRE_NO_RHO | LRE_RHO_FP32
+ * (applied to every instance).  The instance array is copied; the buffers it points
+ * to must stay valid while the plan is used.  Allocates the device work list.
+ * Errors: LRE_E_ARG (bad instance: n, pointer, alignment, shots == 0 or too large),
+ * LRE_E_UNSUPPORTED, LRE_E_HIP. */
+lre_status lre_batch_plan(lre_ctx* ctx, const lre_instance* inst, int count, uint32_t flags,
+                          lre_batch** plan_out);
+
+/* Device workspace bytes lre_batch_run needs (counters and every instance's
+ * intermediate buffers); 0 for a NULL plan. */
+size_t lre_batch_workspace_bytes(const lre_batch* plan);
+
+/* Replace the plan's work-item shape and rebuild its work list (synchronous: waits
+ * for the upload).  Errors: LRE_E_ARG for out-of-range fields, LRE_E_HIP. */
+lre_status lre_batch_set_tiles(lre_batch* plan, const lre_batch_tiles* tiles);
+
+/* The plan's current work-item shape and work-item count. */
+lre_status lre_batch_get_tiles(const lre_batch* plan, lre_batch_tiles* tiles, int* num_items);
+
+/* Autotuner: runs the batch (lre_batch_run) for each candidate work-item shape,
+ * `reps` timed runs each after one warm-up, keeps the fastest shape and returns its
+ * mean time in *best_ms (may be NULL).  Synchronous on `stream`; overwrites the
+ * instances' outputs.  workspace as for lre_batch_run. */
+lre_status lre_batch_tune(lre_batch* plan, void* workspace, size_t workspace_bytes, int reps,
+                          double* best_ms, void* stream);
+
+/* Enqueue the whole batch on `stream` (see above).  workspace: device memory of at
+ * least lre_batch_workspace_bytes(plan) bytes, 256-byte aligned; calls that share a
+ * workspace must be ordered on one stream.  Data errors go to the context's flag
+ * word (lre_check). */
+lre_status lre_batch_run(lre_batch* plan, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Free the plan and its work list (NULL is ignored). */
+void lre_batch_destroy(lre_batch* plan);
 
 #ifdef __cplusplus
 }

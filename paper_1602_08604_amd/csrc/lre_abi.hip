@@ -7,22 +7,14 @@
 #include <cstring>
 
 #include "lre.h"
+#include "lre_internal.hpp"
 #include "lre_kernels.hpp"
 
 using namespace lre;
+using lre_detail::aligned;
+using lre_detail::DeviceGuard;
+using lre_detail::record_stage;
 
-struct lre_ctx {
-  int device;
-  uint32_t* flags;              // device word: FLAG_* bits raised by the kernels
-  hipEvent_t stage_events[4];   // optional profiling events (lre_set_stage_events)
-  int n_stage_events;
-};
-
-namespace {
-void record_stage(lre_ctx* ctx, int k, hipStream_t st) {
-  if (k < ctx->n_stage_events && ctx->stage_events[k]) (void)hipEventRecord(ctx->stage_events[k], st);
-}
-}  // namespace
 
 namespace {
 
@@ -311,20 +303,6 @@ void launch_rho(const Plan& P, const double* coef, void* rho, char* ws, hipStrea
                      (const double2*)tmp, rho, n, (int)kRhoJ);
 }
 
-struct DeviceGuard {
-  int prev = -1;
-  bool ok = true;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) != hipSuccess) { ok = false; return; }
-    if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
-  }
-  ~DeviceGuard() {
-    int cur = -1;
-    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-  }
-};
-
-bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
 // Step (i) into `final_out` (coef or T) with final mode `fm`.
 lre_status run_step1(lre_ctx* ctx, const Plan& P, const uint16_t* counts, uint64_t shots,
@@ -390,6 +368,7 @@ const char* lre_status_str(int s) {
     case LRE_E_SHOTS: return "a basis row does not sum to its declared total";
     case LRE_E_EMPTY_BASIS: return "a basis has zero counts";
     case LRE_E_UNSUPPORTED: return "unsupported request";
+    case LRE_E_TIMEOUT: return "a batched run's bounded wait expired";
     default: return "unknown status";
   }
 }
@@ -476,6 +455,7 @@ lre_status lre_check(lre_ctx* ctx, void* stream) {
     const uint32_t zero = 0;
     if (hipMemcpy(ctx->flags, &zero, sizeof zero, hipMemcpyHostToDevice) != hipSuccess) return LRE_E_HIP;
   }
+  if (f & FLAG_WAIT) return LRE_E_TIMEOUT;
   if (f & FLAG_ARG) return LRE_E_ARG;
   if (f & FLAG_EMPTY) return LRE_E_EMPTY_BASIS;
   if (f & FLAG_SHOTS) return LRE_E_SHOTS;

@@ -1,0 +1,524 @@
+// lre_batch.hip -- batched estimation (lre_batch_* in include/lre.h): many independent
+// instances of steps (i) and (ii) in one persistent kernel driven by a work list.
+//
+// The work of an instance is the same sequence of blocks the single-instance launches
+// run (lre_kernels.hpp): counts-pass tiles, the later fold pass (n > 7), the row-total
+// check, the low and high step-(ii) transforms.  The host cuts every stage into work
+// items (ranges of those blocks), orders them so that an item only ever depends on
+// items listed before it, and uploads the list.  Each persistent workgroup takes the
+// next item (one atomic counter), waits until the items it depends on have finished
+// (per-instance, per-stage completion counters), runs it and bumps its own stage's
+// counter.  Because items are taken in list order by running workgroups, every item
+// an item waits for has already been taken by a running workgroup, so every wait ends;
+// the wait is bounded anyway (FLAG_WAIT) so that no wave can spin forever.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "lre.h"
+#include "lre_internal.hpp"
+#include "lre_kernels.hpp"
+
+using namespace lre;
+using lre_detail::aligned;
+using lre_detail::DeviceGuard;
+
+namespace {
+
+constexpr int kBT = 432;          // threads of a persistent workgroup (27 row groups of 16 lanes)
+constexpr int kQ = 7;             // counts-pass tile qubits (n >= 7)
+constexpr int kJ = 6;             // low step-(ii) qubits (n > 6)
+constexpr int kXB = 64;           // step-(ii) high transform: row entries per block
+constexpr uint32_t kWaitLimit = 1u << 24;  // sleeps of ~64 clocks before a wait gives up
+
+enum Kind : uint8_t { K_COUNTS = 0, K_CHECK = 1, K_FOLD = 2, K_RHO_LOW = 3, K_RHO_HIGH = 4 };
+// variant bits
+enum : uint8_t { V_FINAL = 8, V_MAD24 = 16, V_FP32 = 32 };
+
+struct BItem {
+  int32_t inst;
+  uint8_t kind, variant, pad0, pad1;
+  int32_t wait_ctr;      // completion counter to wait for (-1: none)
+  uint32_t wait_target;  // value it must reach
+  int32_t done_ctr;      // counter to increment when done (-1: none)
+  int32_t pad2;
+  int64_t begin, end;    // block / column / basis range
+};
+
+struct BInst {
+  const uint16_t* counts;
+  double* coef;
+  void* rho;
+  uint64_t shots;
+  int64_t off_part, off_rowpart, off_tmp;  // workspace offsets
+  int32_t n, q1;
+};
+
+constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
+constexpr size_t kLdsCounts = (size_t)StreamGeom<kQ>::NACC * 4 + (size_t)StreamGeom<kQ>::NROWS * 4;
+constexpr size_t kLdsRhoLow = 2 * (size_t)RhoLowLds<kJ>::SIZE * 8;
+constexpr size_t kLdsRhoHigh = 2 * (size_t)kXB * ((1 << (LRE_BATCH_MAX_QUBITS - kJ)) + 1) * 8;
+constexpr size_t kLds = cmax(kLdsCounts, cmax(kLdsRhoLow, kLdsRhoHigh));
+
+template <int Q, bool FINAL, bool MAD24>
+__device__ __noinline__ void run_counts_v(const BInst& I, int64_t b0, int64_t b1, int tid, char* ws, char* smem) {
+  uint32_t* acc = reinterpret_cast<uint32_t*>(smem);
+  uint32_t* rs = acc + StreamGeom<Q>::NACC;
+  uint32_t* rowpart = reinterpret_cast<uint32_t*>(ws + I.off_rowpart);
+  void* out = FINAL ? (void*)I.coef : (void*)(ws + I.off_part);
+  constexpr Out M = FINAL ? Out::CoefUniform : Out::Partial;
+  for (int64_t blk = b0; blk < b1; ++blk) {
+    counts_block<Q, kBT, uint32_t, false, M, MAD24>(I.counts, I.n, 1, nullptr, out, rowpart, I.shots, blk, tid,
+                                                    acc, rs);
+    __syncthreads();  // the next tile clears the LDS this one still reads
+  }
+}
+
+// Instances with n < 7 fold everything in one tile (final output, exact negation path).
+__device__ __forceinline__ void run_counts(const BInst& I, uint8_t var, int64_t b0, int64_t b1, int tid, char* ws,
+                                           char* smem) {
+  const bool fin = (var & V_FINAL) != 0, mad = (var & V_MAD24) != 0;
+  switch (var & 7) {
+    case 1: run_counts_v<1, true, false>(I, b0, b1, tid, ws, smem); break;
+    case 2: run_counts_v<2, true, false>(I, b0, b1, tid, ws, smem); break;
+    case 3: run_counts_v<3, true, false>(I, b0, b1, tid, ws, smem); break;
+    case 4: run_counts_v<4, true, false>(I, b0, b1, tid, ws, smem); break;
+    case 5: run_counts_v<5, true, false>(I, b0, b1, tid, ws, smem); break;
+    case 6: run_counts_v<6, true, false>(I, b0, b1, tid, ws, smem); break;
+    default:
+      if (fin) {
+        if (mad) run_counts_v<7, true, true>(I, b0, b1, tid, ws, smem);
+        else run_counts_v<7, true, false>(I, b0, b1, tid, ws, smem);
+      } else {
+        if (mad) run_counts_v<7, false, true>(I, b0, b1, tid, ws, smem);
+        else run_counts_v<7, false, false>(I, b0, b1, tid, ws, smem);
+      }
+      break;
+  }
+}
+
+__device__ __noinline__ void run_fold(const BInst& I, uint8_t var, int64_t c0, int64_t c1, int tid, char* ws) {
+  const uint32_t* in = reinterpret_cast<const uint32_t*>(ws + I.off_part);
+  const int h = I.n - kQ;
+  for (int64_t col = c0 + tid; col < c1; col += kBT) {
+    if ((var & 7) == 1)
+      fold_partial_col<1, uint32_t, uint32_t, Out::CoefUniform>(in, I.coef, I.n, h, kQ, I.shots, col);
+    else
+      fold_partial_col<2, uint32_t, uint32_t, Out::CoefUniform>(in, I.coef, I.n, h, kQ, I.shots, col);
+  }
+}
+
+template <int J, typename OutT>
+__device__ __noinline__ void run_rho_low_j(const BInst& I, bool fin, int64_t a0, int64_t a1, int tid, char* ws,
+                                              double* re, double* im) {
+  for (int64_t a = a0; a < a1; ++a) {
+    if constexpr (J == kJ) {
+      if (fin) rho_low_block<J, true, OutT, kBT>(I.coef, I.rho, I.n, a, tid, re, im);
+      else rho_low_block<J, false, OutT, kBT>(I.coef, ws + I.off_tmp, I.n, a, tid, re, im);
+    } else {
+      rho_low_block<J, true, OutT, kBT>(I.coef, I.rho, I.n, a, tid, re, im);
+    }
+    __syncthreads();
+  }
+}
+
+template <typename OutT>
+__device__ __forceinline__ void run_rho_low(const BInst& I, uint8_t var, int64_t a0, int64_t a1, int tid, char* ws,
+                                            double* re, double* im) {
+  const bool fin = (var & V_FINAL) != 0;
+  switch (var & 7) {
+    case 1: run_rho_low_j<1, OutT>(I, fin, a0, a1, tid, ws, re, im); break;
+    case 2: run_rho_low_j<2, OutT>(I, fin, a0, a1, tid, ws, re, im); break;
+    case 3: run_rho_low_j<3, OutT>(I, fin, a0, a1, tid, ws, re, im); break;
+    case 4: run_rho_low_j<4, OutT>(I, fin, a0, a1, tid, ws, re, im); break;
+    case 5: run_rho_low_j<5, OutT>(I, fin, a0, a1, tid, ws, re, im); break;
+    default: run_rho_low_j<6, OutT>(I, fin, a0, a1, tid, ws, re, im); break;
+  }
+}
+
+template <typename OutT>
+__device__ __noinline__ void run_rho_high(const BInst& I, int64_t b0, int64_t b1, int tid, char* ws, double* re,
+                                             double* im) {
+  const double2* tmp = reinterpret_cast<const double2*>(ws + I.off_tmp);
+  for (int64_t b = b0; b < b1; ++b) {
+    rho_high_block<kXB, OutT, kBT>(tmp, I.rho, I.n, kJ, b, tid, re, im);
+    __syncthreads();
+  }
+}
+
+// ctl[0]: next item; ctl[1 + 3 j + k]: completion counter of stage k of instance j.
+__global__ __launch_bounds__(kBT, 4) void batch_kernel(const BItem* __restrict__ items, int nitems,
+                                                      const BInst* __restrict__ insts, char* __restrict__ ws,
+                                                      uint32_t* __restrict__ ctl, uint32_t* __restrict__ flags) {
+  __shared__ __align__(16) char smem[kLds];
+  __shared__ int s_item;
+  __shared__ int s_skip;
+  const int tid = threadIdx.x;
+  double* re = reinterpret_cast<double*>(smem);
+  double* im = re + (kLds / 16);
+  for (;;) {
+    if (tid == 0) s_item = (int)atomicAdd(&ctl[0], 1u);
+    __syncthreads();
+    const int it = s_item;
+    if (it >= nitems) break;
+    const BItem W = items[it];
+    if (tid == 0) {
+      int skip = 0;
+      if (W.wait_ctr >= 0) {
+        uint32_t spins = 0;
+        while (__hip_atomic_load(&ctl[W.wait_ctr], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < W.wait_target) {
+          if (++spins > kWaitLimit) {
+            atomicOr(flags, (uint32_t)FLAG_WAIT);
+            skip = 1;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+      s_skip = skip;
+    }
+    __syncthreads();
+    // Acquire: the producers' results become visible to every thread of this workgroup.
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (!s_skip) {
+      const BInst I = insts[W.inst];
+      switch (W.kind) {
+        case K_COUNTS: run_counts(I, W.variant, W.begin, W.end, tid, ws, smem); break;
+        case K_CHECK: {
+          const int64_t rows = ipow3(I.q1);
+          const int64_t runs = (int64_t)1 << (I.n - I.q1);
+          const uint32_t* rowpart = reinterpret_cast<const uint32_t*>(ws + I.off_rowpart);
+          for (int64_t b = W.begin + tid; b < W.end; b += kBT) check_row(rowpart, rows, runs, nullptr, I.shots, b, flags);
+          break;
+        }
+        case K_FOLD: run_fold(I, W.variant, W.begin, W.end, tid, ws); break;
+        case K_RHO_LOW:
+          if (W.variant & V_FP32) run_rho_low<float>(I, W.variant, W.begin, W.end, tid, ws, re, im);
+          else run_rho_low<double>(I, W.variant, W.begin, W.end, tid, ws, re, im);
+          break;
+        default:
+          if (W.variant & V_FP32) run_rho_high<float>(I, W.begin, W.end, tid, ws, re, im);
+          else run_rho_high<double>(I, W.begin, W.end, tid, ws, re, im);
+          break;
+      }
+    }
+    // Release: this workgroup's results are visible device-wide before the counter moves.
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (tid == 0 && W.done_ctr >= 0)
+      __hip_atomic_fetch_add(&ctl[W.done_ctr], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+struct InstMeta {
+  int n = 0, q1 = 0, F = 0;     // F: later-pass qubits (n - 7 when n > 7)
+  int64_t blocks1 = 0;          // counts-pass tiles
+  bool mad24 = false;
+  int64_t counts = 0;           // 6^n, the ordering key
+};
+
+}  // namespace
+
+struct lre_batch {
+  lre_ctx* ctx = nullptr;
+  uint32_t flags = 0;
+  std::vector<lre_instance> inst;
+  std::vector<InstMeta> meta;
+  std::vector<BInst> dinst_host;
+  lre_batch_tiles tiles{};
+  BInst* d_inst = nullptr;
+  BItem* d_items = nullptr;
+  size_t items_cap = 0;
+  int nitems = 0;
+  size_t ctl_bytes = 0;
+  size_t ws_bytes = 0;
+  int num_cu = 0;
+};
+
+namespace {
+
+bool valid_tiles(const lre_batch_tiles& t) {
+  return (t.workers_per_cu == 1 || t.workers_per_cu == 2) && t.counts_tiles >= 1 && t.fold_cols >= kBT &&
+         t.fold_cols % kBT == 0 && t.rho_blocks >= 1 && (t.interleave == 0 || t.interleave == 1);
+}
+
+void add_range(std::vector<BItem>& out, int inst, Kind kind, uint8_t var, int64_t total, int64_t per,
+               int32_t wait_ctr, uint32_t wait_target, int32_t done_ctr, uint32_t* count_out) {
+  uint32_t c = 0;
+  for (int64_t b = 0; b < total; b += per) {
+    BItem W{};
+    W.inst = inst;
+    W.kind = kind;
+    W.variant = var;
+    W.wait_ctr = wait_ctr;
+    W.wait_target = wait_target;
+    W.done_ctr = done_ctr;
+    W.begin = b;
+    W.end = std::min(total, b + per);
+    out.push_back(W);
+    ++c;
+  }
+  if (count_out) *count_out = c;
+}
+
+// Work items of instance j for one stage (0 counts, 1 check + fold, 2 rho low, 3 rho high).
+struct StageCounts {
+  uint32_t counts = 0, fold = 0, rho_low = 0;
+};
+
+void emit_stage(const lre_batch& B, int j, int stage, std::vector<BItem>& out, StageCounts& sc) {
+  const InstMeta& m = B.meta[j];
+  const lre_batch_tiles& t = B.tiles;
+  const bool want_rho = !(B.flags & LRE_NO_RHO);
+  const uint8_t fp32 = (B.flags & LRE_RHO_FP32) ? V_FP32 : 0;
+  const int32_t c_counts = 1 + 3 * j, c_fold = 2 + 3 * j, c_low = 3 + 3 * j;
+  switch (stage) {
+    case 0: {
+      const uint8_t var = (uint8_t)(m.q1 | (m.F == 0 ? V_FINAL : 0) | (m.mad24 ? V_MAD24 : 0));
+      add_range(out, j, K_COUNTS, var, m.blocks1, t.counts_tiles, -1, 0, c_counts, &sc.counts);
+      break;
+    }
+    case 1: {
+      const int64_t nb = ipow3(m.n);
+      add_range(out, j, K_CHECK, 0, nb, std::max<int64_t>(nb, 1), c_counts, sc.counts, -1, nullptr);
+      if (m.F > 0) {
+        const int64_t ncols = ipow4(kQ);  // one later pass folds all n - 7 remaining qubits
+        add_range(out, j, K_FOLD, (uint8_t)m.F, ncols, t.fold_cols, c_counts, sc.counts, c_fold, &sc.fold);
+      }
+      break;
+    }
+    case 2: {
+      if (!want_rho) break;
+      const int J = m.n < kJ ? m.n : kJ;
+      const bool fin = m.n <= kJ;
+      const int32_t wc = m.F > 0 ? c_fold : c_counts;
+      const uint32_t wt = m.F > 0 ? sc.fold : sc.counts;
+      add_range(out, j, K_RHO_LOW, (uint8_t)(J | (fin ? V_FINAL : 0) | fp32), ipow4(m.n - J), t.rho_blocks, wc, wt,
+                c_low, &sc.rho_low);
+      break;
+    }
+    default: {
+      if (!want_rho || m.n <= kJ) break;
+      const int64_t D = (int64_t)1 << kJ;
+      const int64_t blocks = ((int64_t)1 << (m.n - kJ)) * D * (D / kXB);
+      add_range(out, j, K_RHO_HIGH, fp32, blocks, t.rho_blocks, c_low, sc.rho_low, -1, nullptr);
+      break;
+    }
+  }
+}
+
+lre_status rebuild(lre_batch& B) {
+  const int count = (int)B.inst.size();
+  std::vector<int> order(count);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return B.meta[a].counts > B.meta[b].counts; });
+  std::vector<BItem> items;
+  std::vector<StageCounts> sc(count);
+  if (B.tiles.interleave) {
+    for (int j : order)
+      for (int s = 0; s < 4; ++s) emit_stage(B, j, s, items, sc[j]);
+  } else {
+    for (int s = 0; s < 4; ++s)
+      for (int j : order) emit_stage(B, j, s, items, sc[j]);
+  }
+  if (items.size() > (size_t)INT32_MAX) return LRE_E_UNSUPPORTED;
+  DeviceGuard g(B.ctx->device);
+  if (!g.ok) return LRE_E_HIP;
+  // A run still in flight may read the current list: wait before replacing it.
+  if (B.d_items && hipDeviceSynchronize() != hipSuccess) return LRE_E_HIP;
+  if (items.size() > B.items_cap) {
+    if (B.d_items) (void)hipFree(B.d_items);
+    B.d_items = nullptr;
+    B.items_cap = 0;
+    if (hipMalloc(&B.d_items, items.size() * sizeof(BItem)) != hipSuccess) return LRE_E_HIP;
+    B.items_cap = items.size();
+  }
+  if (!items.empty() &&
+      hipMemcpy(B.d_items, items.data(), items.size() * sizeof(BItem), hipMemcpyHostToDevice) != hipSuccess)
+    return LRE_E_HIP;
+  B.nitems = (int)items.size();
+  return LRE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lre_status lre_batch_plan(lre_ctx* ctx, const lre_instance* inst, int count, uint32_t flags,
+                          lre_batch** plan_out) {
+  if (!plan_out) return LRE_E_ARG;
+  *plan_out = nullptr;
+  if (!ctx || !inst || count < 1) return LRE_E_ARG;
+  if (flags & ~(LRE_NO_RHO | LRE_RHO_FP32)) return LRE_E_ARG;
+  const bool want_rho = !(flags & LRE_NO_RHO);
+  for (int j = 0; j < count; ++j) {
+    const lre_instance& I = inst[j];
+    if (I.n < 1 || !I.counts || !I.coef || !aligned(I.counts, 16) || !aligned(I.coef, 8)) return LRE_E_ARG;
+    if (I.n > LRE_BATCH_MAX_QUBITS) return LRE_E_UNSUPPORTED;
+    if (I.shots == 0) return LRE_E_UNSUPPORTED;
+    if ((long double)I.shots * (long double)ipow3(I.n) > (long double)INT32_MAX) return LRE_E_ARG;
+    if (want_rho && (!I.rho || !aligned(I.rho, 16))) return LRE_E_ARG;
+  }
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return LRE_E_HIP;
+  lre_batch* B = new (std::nothrow) lre_batch;
+  if (!B) return LRE_E_HIP;
+  B->ctx = ctx;
+  B->flags = flags;
+  B->inst.assign(inst, inst + count);
+  B->meta.resize(count);
+  B->dinst_host.resize(count);
+  if (hipDeviceGetAttribute(&B->num_cu, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess ||
+      B->num_cu < 1) {
+    delete B;
+    return LRE_E_HIP;
+  }
+  B->ctl_bytes = align256((size_t)(1 + 3 * (size_t)count) * 4);
+  size_t off = B->ctl_bytes;
+  for (int j = 0; j < count; ++j) {
+    const lre_instance& I = inst[j];
+    InstMeta& m = B->meta[j];
+    m.n = I.n;
+    m.q1 = I.n < kQ ? I.n : kQ;
+    m.F = I.n > kQ ? I.n - kQ : 0;
+    m.blocks1 = ipow3(I.n - m.q1) << (I.n - m.q1);
+    m.mad24 = m.q1 == kQ && 27ull * I.shots < (1ull << 23);
+    m.counts = ipow3(I.n) << I.n;
+    BInst& d = B->dinst_host[j];
+    d.counts = I.counts;
+    d.coef = I.coef;
+    d.rho = I.rho;
+    d.shots = I.shots;
+    d.n = I.n;
+    d.q1 = m.q1;
+    d.off_part = 0;
+    if (m.F > 0) {
+      d.off_part = (int64_t)off;
+      off += align256((size_t)m.blocks1 * (size_t)ipow4(kQ) * 4);
+    }
+    d.off_rowpart = (int64_t)off;
+    off += align256((size_t)m.blocks1 * (size_t)ipow3(m.q1) * 4);
+    d.off_tmp = 0;
+    if (want_rho && I.n > kJ) {
+      d.off_tmp = (int64_t)off;
+      off += align256((size_t)ipow4(I.n) * 16);
+    }
+  }
+  B->ws_bytes = off;
+  if (hipMalloc(&B->d_inst, count * sizeof(BInst)) != hipSuccess) {
+    delete B;
+    return LRE_E_HIP;
+  }
+  if (hipMemcpy(B->d_inst, B->dinst_host.data(), count * sizeof(BInst), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(B->d_inst);
+    delete B;
+    return LRE_E_HIP;
+  }
+  B->tiles = lre_batch_tiles{2, 2, kBT * 8, 8, 0};
+  const lre_status s = rebuild(*B);
+  if (s != LRE_OK) {
+    lre_batch_destroy(B);
+    return s;
+  }
+  *plan_out = B;
+  return LRE_OK;
+}
+
+size_t lre_batch_workspace_bytes(const lre_batch* plan) { return plan ? plan->ws_bytes : 0; }
+
+lre_status lre_batch_set_tiles(lre_batch* plan, const lre_batch_tiles* tiles) {
+  if (!plan || !tiles || !valid_tiles(*tiles)) return LRE_E_ARG;
+  plan->tiles = *tiles;
+  return rebuild(*plan);
+}
+
+lre_status lre_batch_get_tiles(const lre_batch* plan, lre_batch_tiles* tiles, int* num_items) {
+  if (!plan) return LRE_E_ARG;
+  if (tiles) *tiles = plan->tiles;
+  if (num_items) *num_items = plan->nitems;
+  return LRE_OK;
+}
+
+lre_status lre_batch_run(lre_batch* plan, void* workspace, size_t workspace_bytes, void* stream) {
+  if (!plan) return LRE_E_ARG;
+  if (!workspace || !aligned(workspace, 256)) return LRE_E_ARG;
+  if (workspace_bytes < plan->ws_bytes) return LRE_E_WORKSPACE;
+  DeviceGuard g(plan->ctx->device);
+  if (!g.ok) return LRE_E_HIP;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  uint32_t* ctl = reinterpret_cast<uint32_t*>(ws);
+  const int64_t words = 1 + 3 * (int64_t)plan->inst.size();
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, st, ctl, words, 0u);
+  const int workers = plan->num_cu * plan->tiles.workers_per_cu;
+  hipLaunchKernelGGL(batch_kernel, dim3((unsigned)workers), dim3(kBT), 0, st, (const BItem*)plan->d_items,
+                     plan->nitems, (const BInst*)plan->d_inst, ws, ctl, plan->ctx->flags);
+  return hipGetLastError() == hipSuccess ? LRE_OK : LRE_E_HIP;
+}
+
+lre_status lre_batch_tune(lre_batch* plan, void* workspace, size_t workspace_bytes, int reps, double* best_ms,
+                          void* stream) {
+  if (!plan || reps < 1) return LRE_E_ARG;
+  DeviceGuard g(plan->ctx->device);
+  if (!g.ok) return LRE_E_HIP;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return LRE_E_HIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return LRE_E_HIP;
+  }
+  const lre_batch_tiles start = plan->tiles;
+  lre_batch_tiles best = start;
+  double best_t = 1e300;
+  lre_status s = LRE_OK;
+  for (int w : {1, 2})
+    for (int ct : {1, 2, 4})
+      for (int fc : {kBT * 4, kBT * 16})
+        for (int rb : {4, 16})
+          for (int il : {0, 1}) {
+            const lre_batch_tiles t{w, ct, fc, rb, il};
+            if ((s = lre_batch_set_tiles(plan, &t)) != LRE_OK) goto done;
+            if ((s = lre_batch_run(plan, workspace, workspace_bytes, stream)) != LRE_OK) goto done;
+            if (hipEventRecord(e0, st) != hipSuccess) { s = LRE_E_HIP; goto done; }
+            for (int r = 0; r < reps; ++r)
+              if ((s = lre_batch_run(plan, workspace, workspace_bytes, stream)) != LRE_OK) goto done;
+            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+              s = LRE_E_HIP;
+              goto done;
+            }
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { s = LRE_E_HIP; goto done; }
+            const double t_ms = (double)ms / reps;
+            if (t_ms < best_t) {
+              best_t = t_ms;
+              best = t;
+            }
+          }
+done:
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  const lre_status s2 = lre_batch_set_tiles(plan, s == LRE_OK ? &best : &start);
+  if (s == LRE_OK) s = s2;
+  if (s == LRE_OK && best_ms) *best_ms = best_t;
+  return s;
+}
+
+void lre_batch_destroy(lre_batch* plan) {
+  if (!plan) return;
+  {
+    DeviceGuard g(plan->ctx->device);
+    if (plan->d_items) (void)hipFree(plan->d_items);
+    if (plan->d_inst) (void)hipFree(plan->d_inst);
+  }
+  delete plan;
+}
+
+}  // extern "C"

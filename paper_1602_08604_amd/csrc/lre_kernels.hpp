@@ -43,7 +43,7 @@ __host__ __device__ constexpr int64_t ipow3(int k) { return k <= 0 ? 1 : 3 * ipo
 __host__ __device__ constexpr int64_t ipow4(int k) { return k <= 0 ? 1 : 4 * ipow4(k - 1); }
 __host__ __device__ constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
 
-enum : uint32_t { FLAG_SHOTS = 1u, FLAG_EMPTY = 2u, FLAG_ARG = 4u };
+enum : uint32_t { FLAG_SHOTS = 1u, FLAG_EMPTY = 2u, FLAG_ARG = 4u, FLAG_WAIT = 8u };
 
 // What the final pass writes.
 enum class Out : int { Partial = 0, CoefUniform = 1, CoefPerBasis = 2, PauliT = 3 };
@@ -355,22 +355,23 @@ __device__ __forceinline__ uint32_t stream_slot(uint32_t a) {
   return stream_slot_of<Q, LB>(a & ((1u << (2 * LB)) - 1), a >> (2 * LB));
 }
 
-template <int Q, int THREADS, typename Acc, bool PER_BASIS, Out MODE, bool MAD24, int MINWAVES = 1>
-__global__ __launch_bounds__(THREADS, MINWAVES) void fold_counts_stream_kernel(
-    const uint16_t* __restrict__ counts, int n, int chunks, const uint32_t* __restrict__ nb,
-    void* __restrict__ out, uint32_t* __restrict__ rowpart, uint64_t shots) {
+// One block of the counts pass: block index `blk` -> (b_hi, run of `chunks` s_hi tiles).
+// acc / rs_acc: LDS of NACC accumulators and NROWS row totals.  Every thread of the
+// block calls this (it synchronises the block).
+template <int Q, int THREADS, typename Acc, bool PER_BASIS, Out MODE, bool MAD24>
+__device__ __forceinline__ void counts_block(const uint16_t* __restrict__ counts, int n, int chunks,
+                                             const uint32_t* __restrict__ nb, void* __restrict__ out,
+                                             uint32_t* __restrict__ rowpart, uint64_t shots, int64_t blk,
+                                             int tid, Acc* __restrict__ acc, uint32_t* __restrict__ rs_acc) {
   using G = StreamGeom<Q>;
   constexpr int GROUPS = THREADS / G::LPC;
   constexpr int LB = G::LB;
-  __shared__ Acc acc[G::NACC];
-  __shared__ uint32_t rs_acc[G::NROWS];
 
-  const int tid = threadIdx.x;
   const int grp = tid / G::LPC, lam = tid % G::LPC;
   const int64_t n_shi = (int64_t)1 << (n - Q);
   const int64_t runs_per_row = n_shi / chunks;
-  const int64_t b_hi = blockIdx.x / runs_per_row;
-  const int64_t s_hi0 = (blockIdx.x % runs_per_row) * chunks;
+  const int64_t b_hi = blk / runs_per_row;
+  const int64_t s_hi0 = (blk % runs_per_row) * chunks;
   const int64_t row0 = b_hi * G::NROWS;
   const int64_t rowlen = (int64_t)1 << n;
 
@@ -524,8 +525,18 @@ __global__ __launch_bounds__(THREADS, MINWAVES) void fold_counts_stream_kernel(
     __syncthreads();
   }
 
-  uint32_t* __restrict__ rp = rowpart + (int64_t)blockIdx.x * G::NROWS;
+  uint32_t* __restrict__ rp = rowpart + blk * G::NROWS;
   for (int i = tid; i < G::NROWS; i += THREADS) rp[i] = rs_acc[i];
+}
+
+template <int Q, int THREADS, typename Acc, bool PER_BASIS, Out MODE, bool MAD24, int MINWAVES = 1>
+__global__ __launch_bounds__(THREADS, MINWAVES) void fold_counts_stream_kernel(
+    const uint16_t* __restrict__ counts, int n, int chunks, const uint32_t* __restrict__ nb,
+    void* __restrict__ out, uint32_t* __restrict__ rowpart, uint64_t shots) {
+  __shared__ Acc acc[StreamGeom<Q>::NACC];
+  __shared__ uint32_t rs_acc[StreamGeom<Q>::NROWS];
+  counts_block<Q, THREADS, Acc, PER_BASIS, MODE, MAD24>(counts, n, chunks, nb, out, rowpart, shots,
+                                                       blockIdx.x, threadIdx.x, acc, rs_acc);
 }
 
 // ---------------------------------------------------------------------------------
@@ -756,12 +767,11 @@ __device__ __forceinline__ Acc in_to_acc(Tin v) {
   else return (Acc)v;
 }
 
+// One column of a later pass: folds F more qubits of the partial tensor for the
+// fastest-varying index column `col` (one thread per column, all in registers).
 template <int F, typename Tin, typename Acc, Out MODE>
-__global__ __launch_bounds__(256) void fold_partial_kernel(const Tin* __restrict__ in,
-                                                           void* __restrict__ out, int n, int h,
-                                                           int l, uint64_t shots, int64_t ncols) {
-  const int64_t col = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (col >= ncols) return;
+__device__ __forceinline__ void fold_partial_col(const Tin* __restrict__ in, void* __restrict__ out, int n,
+                                                 int h, int l, uint64_t shots, int64_t col) {
   const int64_t L = (int64_t)1 << (2 * l);
   const int64_t a_l = col & (L - 1);
   const int64_t bs = col >> (2 * l);
@@ -809,16 +819,24 @@ __global__ __launch_bounds__(256) void fold_partial_kernel(const Tin* __restrict
   }
 }
 
+template <int F, typename Tin, typename Acc, Out MODE>
+__global__ __launch_bounds__(256) void fold_partial_kernel(const Tin* __restrict__ in,
+                                                           void* __restrict__ out, int n, int h,
+                                                           int l, uint64_t shots, int64_t ncols) {
+  const int64_t col = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (col < ncols) fold_partial_col<F, Tin, Acc, MODE>(in, out, n, h, l, shots, col);
+}
+
 // ---------------------------------------------------------------------------------
 // Row totals: zero fill, per-basis totals (when not supplied), and the final check.
 
-__global__ void fill_u32_kernel(uint32_t* __restrict__ p, int64_t count, uint32_t v) {
+static __global__ void fill_u32_kernel(uint32_t* __restrict__ p, int64_t count, uint32_t v) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i < count) p[i] = v;
 }
 
 // One block of 256 threads per basis row.
-__global__ __launch_bounds__(256) void row_totals_kernel(const uint16_t* __restrict__ counts,
+static __global__ __launch_bounds__(256) void row_totals_kernel(const uint16_t* __restrict__ counts,
                                                          int n, uint32_t* __restrict__ nb) {
   const int64_t b = blockIdx.x;
   const int64_t d = (int64_t)1 << n;
@@ -834,17 +852,22 @@ __global__ __launch_bounds__(256) void row_totals_kernel(const uint16_t* __restr
 }
 
 // rowpart as written by fold_counts_kernel: [3^n / rows][runs][rows].
-__global__ void check_rows_kernel(const uint32_t* __restrict__ rowpart, int64_t rows, int64_t runs,
-                                  const uint32_t* __restrict__ nb, uint64_t shots,
-                                  int64_t nbases, uint32_t* __restrict__ flags) {
-  const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (b >= nbases) return;
+__device__ __forceinline__ void check_row(const uint32_t* __restrict__ rowpart, int64_t rows, int64_t runs,
+                                          const uint32_t* __restrict__ nb, uint64_t shots, int64_t b,
+                                          uint32_t* __restrict__ flags) {
   const int64_t grp = b / rows, j = b % rows;
   uint64_t tot = 0;
   for (int64_t r = 0; r < runs; ++r) tot += rowpart[(grp * runs + r) * rows + j];
   const uint64_t want = shots ? shots : (uint64_t)nb[b];
   if (tot != want) atomicOr(flags, (uint32_t)FLAG_SHOTS);
   if (!shots && want == 0) atomicOr(flags, (uint32_t)FLAG_EMPTY);
+}
+
+static __global__ void check_rows_kernel(const uint32_t* __restrict__ rowpart, int64_t rows, int64_t runs,
+                                  const uint32_t* __restrict__ nb, uint64_t shots,
+                                  int64_t nbases, uint32_t* __restrict__ flags) {
+  const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (b < nbases) check_row(rowpart, rows, runs, nb, shots, b, flags);
 }
 
 // ---------------------------------------------------------------------------------
@@ -913,16 +936,22 @@ __device__ __forceinline__ void store_complex(void* base, int64_t idx, double re
 
 // Transform the low J qubits of one 4^J block of coefficients (block = high letters).
 // FINAL (J == n): writes mu directly.  Otherwise tmp[a_hi][r_lo][x_lo] (complex128).
-template <int J, bool FINAL, typename OutT>
-__global__ __launch_bounds__(256) void rho_low_kernel(const double* __restrict__ coef,
-                                                      void* __restrict__ out, int n) {
+template <int J>
+struct RhoLowLds {
+  static constexpr int D = 1 << J;
+  static constexpr int DP = D + 1;  // padded row stride (spreads the rows over LDS banks)
+  static constexpr int SIZE = D * DP;  // doubles per plane (re, im)
+};
+
+template <int J, bool FINAL, typename OutT, int THREADS>
+__device__ __forceinline__ void rho_low_block(const double* __restrict__ coef, void* __restrict__ out,
+                                              int n, int64_t a_hi, int tid, double* __restrict__ re,
+                                              double* __restrict__ im) {
   constexpr int D = 1 << J;
   constexpr int NN = D * D;
-  constexpr int DP = D + 1;  // padded row stride (spreads the rows over LDS banks)
-  __shared__ double re[D * DP], im[D * DP];  // [x][z], then [x][r]
-  const int64_t a_hi = blockIdx.x;
+  constexpr int DP = RhoLowLds<J>::DP;   // re, im: [x][z], then [x][r]
   const double* __restrict__ e = coef + a_hi * NN;
-  for (int t = threadIdx.x; t < NN; t += 256) {
+  for (int t = tid; t < NN; t += THREADS) {
     int x = 0, z = 0, ny = 0;
 #pragma unroll
     for (int p = 0; p < J; ++p) {
@@ -939,7 +968,7 @@ __global__ __launch_bounds__(256) void rho_low_kernel(const double* __restrict__
   __syncthreads();
 #pragma unroll 1
   for (int bit = 0; bit < J; ++bit) {
-    for (int t = threadIdx.x; t < NN / 2; t += 256) {
+    for (int t = tid; t < NN / 2; t += THREADS) {
       const int x = t / (D / 2), k = t % (D / 2);
       const int lo = ((k >> bit) << (bit + 1)) | (k & ((1 << bit) - 1));
       const int hi = lo | (1 << bit);
@@ -954,36 +983,43 @@ __global__ __launch_bounds__(256) void rho_low_kernel(const double* __restrict__
   }
   if constexpr (FINAL) {
     const double scale = ldexp(1.0, -J);  // 2^-n with n == J
-    for (int t = threadIdx.x; t < NN; t += 256) {
+    for (int t = tid; t < NN; t += THREADS) {
       const int r = t / D, c = t % D, x = r ^ c;
       store_complex<OutT>(out, t, re[x * DP + r] * scale, im[x * DP + r] * scale);
     }
   } else {
     double2* tmp = static_cast<double2*>(out) + a_hi * NN;
-    for (int t = threadIdx.x; t < NN; t += 256) {
+    for (int t = tid; t < NN; t += THREADS) {
       const int r = t / D, x = t % D;
       tmp[t] = make_double2(re[x * DP + r], im[x * DP + r]);
     }
   }
 }
 
+template <int J, bool FINAL, typename OutT>
+__global__ __launch_bounds__(256) void rho_low_kernel(const double* __restrict__ coef,
+                                                      void* __restrict__ out, int n) {
+  __shared__ double re[RhoLowLds<J>::SIZE], im[RhoLowLds<J>::SIZE];
+  rho_low_block<J, FINAL, OutT, 256>(coef, out, n, blockIdx.x, threadIdx.x, re, im);
+}
+
 // Transform the high H = n - J qubits and write mu row-major.  Block -> (x_hi, r_lo,
 // block of XB consecutive x_lo); the XB entries of a row are adjacent in memory.
-template <int XB, int HMAX, typename OutT>
-__global__ __launch_bounds__(256) void rho_high_kernel(const double2* __restrict__ tmp,
-                                                       void* __restrict__ rho, int n, int J) {
-  __shared__ double re[XB * ((1 << HMAX) + 1)], im[XB * ((1 << HMAX) + 1)];  // [xo][z], padded
+// re, im: LDS planes of at least XB * (2^(n-J) + 1) doubles ([xo][z], padded rows).
+template <int XB, typename OutT, int THREADS>
+__device__ __forceinline__ void rho_high_block(const double2* __restrict__ tmp, void* __restrict__ rho,
+                                               int n, int J, int64_t bid, int tid,
+                                               double* __restrict__ re, double* __restrict__ im) {
   const int H = n - J;
   const int NH = 1 << H;
   const int NHP = NH + 1;  // padded row stride
   const int D = 1 << J;
-  int64_t bid = blockIdx.x;
   const int xblk = (int)(bid % (D / XB));
   bid /= (D / XB);
   const int r_lo = (int)(bid % D);
   const int64_t x_hi = bid / D;
   const int tile = NH * XB;
-  for (int t = threadIdx.x; t < tile; t += 256) {
+  for (int t = tid; t < tile; t += THREADS) {
     const int z = t / XB, xo = t % XB;
     const int x_lo = xblk * XB + xo;
     int64_t a_hi = 0;
@@ -999,7 +1035,7 @@ __global__ __launch_bounds__(256) void rho_high_kernel(const double2* __restrict
   }
   __syncthreads();
   for (int bit = 0; bit < H; ++bit) {
-    for (int t = threadIdx.x; t < tile / 2; t += 256) {
+    for (int t = tid; t < tile / 2; t += THREADS) {
       const int xo = t / (NH / 2), k = t % (NH / 2);
       const int lo = ((k >> bit) << (bit + 1)) | (k & ((1 << bit) - 1));
       const int hi = lo | (1 << bit);
@@ -1014,13 +1050,20 @@ __global__ __launch_bounds__(256) void rho_high_kernel(const double2* __restrict
   }
   const double scale = ldexp(1.0, -n);
   const int64_t dn = (int64_t)1 << n;
-  for (int t = threadIdx.x; t < tile; t += 256) {
+  for (int t = tid; t < tile; t += THREADS) {
     const int r_hi = t / XB, xo = t % XB;
     const int x_lo = xblk * XB + xo;
     const int64_t row = ((int64_t)r_hi << J) | r_lo;
     const int64_t col = ((int64_t)(r_hi ^ x_hi) << J) | (r_lo ^ x_lo);
     store_complex<OutT>(rho, row * dn + col, re[xo * NHP + r_hi] * scale, im[xo * NHP + r_hi] * scale);
   }
+}
+
+template <int XB, int HMAX, typename OutT>
+__global__ __launch_bounds__(256) void rho_high_kernel(const double2* __restrict__ tmp,
+                                                       void* __restrict__ rho, int n, int J) {
+  __shared__ double re[XB * ((1 << HMAX) + 1)], im[XB * ((1 << HMAX) + 1)];
+  rho_high_block<XB, OutT, 256>(tmp, rho, n, J, blockIdx.x, threadIdx.x, re, im);
 }
 
 }  // namespace lre

@@ -24,11 +24,23 @@ LRE_E_HIP = 3
 LRE_E_SHOTS = 4
 LRE_E_EMPTY_BASIS = 5
 LRE_E_UNSUPPORTED = 6
+LRE_E_TIMEOUT = 7
 
 LRE_NO_RHO = 0x1
 LRE_RHO_FP32 = 0x2
 LRE_WHT_MFMA = 0x4
 LRE_MAX_QUBITS = 14
+LRE_BATCH_MAX_QUBITS = 9
+
+
+class lre_instance(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("counts", ctypes.c_void_p), ("shots", ctypes.c_uint64),
+                ("coef", ctypes.c_void_p), ("rho", ctypes.c_void_p)]
+
+
+class lre_batch_tiles(ctypes.Structure):
+    _fields_ = [("workers_per_cu", ctypes.c_int), ("counts_tiles", ctypes.c_int),
+                ("fold_cols", ctypes.c_int), ("rho_blocks", ctypes.c_int), ("interleave", ctypes.c_int)]
 
 
 class LreError(RuntimeError):
@@ -69,6 +81,20 @@ def lib():
         L.lre_signed_sums.restype = I
         L.lre_set_stage_events.argtypes = [P, ctypes.POINTER(P), I]
         L.lre_set_stage_events.restype = I
+        L.lre_batch_plan.argtypes = [P, ctypes.POINTER(lre_instance), I, U32, ctypes.POINTER(P)]
+        L.lre_batch_plan.restype = I
+        L.lre_batch_workspace_bytes.argtypes = [P]
+        L.lre_batch_workspace_bytes.restype = SZ
+        L.lre_batch_set_tiles.argtypes = [P, ctypes.POINTER(lre_batch_tiles)]
+        L.lre_batch_set_tiles.restype = I
+        L.lre_batch_get_tiles.argtypes = [P, ctypes.POINTER(lre_batch_tiles), ctypes.POINTER(I)]
+        L.lre_batch_get_tiles.restype = I
+        L.lre_batch_tune.argtypes = [P, P, SZ, I, ctypes.POINTER(ctypes.c_double), P]
+        L.lre_batch_tune.restype = I
+        L.lre_batch_run.argtypes = [P, P, SZ, P]
+        L.lre_batch_run.restype = I
+        L.lre_batch_destroy.argtypes = [P]
+        L.lre_batch_destroy.restype = None
         _lib_handle = L
     return _lib_handle
 
@@ -211,3 +237,90 @@ def set_stage_events(events, device=None):
         return
     arr = (ctypes.c_void_p * len(events))(*events)
     _ok(lib().lre_set_stage_events(ctx, arr, len(events)), "lre_set_stage_events")
+
+
+class Batch:
+    """lre_batch_*: many instances (n <= 9, uniform shots each) in one persistent launch.
+
+    counts: list of uint16 device tensors [3^n, 2^n]; shots: list of ints.  Output tensors
+    are allocated unless given (coef float64 [4^n]; rho complex [2^n, 2^n] unless
+    LRE_NO_RHO).  The plan keeps references to every tensor it points to."""
+
+    def __init__(self, counts, shots, flags=0, coefs=None, rhos=None):
+        if len(counts) != len(shots) or not counts:
+            raise ValueError("counts and shots must be non-empty lists of equal length")
+        self.flags = int(flags)
+        self.counts = list(counts)
+        self.shots = [int(x) for x in shots]
+        dev = self.counts[0].device
+        self.device = dev
+        want_rho = not (flags & LRE_NO_RHO)
+        cdt = torch.complex64 if flags & LRE_RHO_FP32 else torch.complex128
+        self.n = [_check_counts(c) for c in self.counts]
+        self.coefs = list(coefs) if coefs is not None else [
+            torch.empty(4 ** n, dtype=torch.float64, device=dev) for n in self.n]
+        if want_rho:
+            self.rhos = list(rhos) if rhos is not None else [
+                torch.empty((1 << n, 1 << n), dtype=cdt, device=dev) for n in self.n]
+        else:
+            self.rhos = [None] * len(self.n)
+        arr = (lre_instance * len(self.n))()
+        for j, n in enumerate(self.n):
+            arr[j].n = n
+            arr[j].counts = self.counts[j].data_ptr()
+            arr[j].shots = self.shots[j]
+            arr[j].coef = self.coefs[j].data_ptr()
+            arr[j].rho = self.rhos[j].data_ptr() if self.rhos[j] is not None else None
+        h = ctypes.c_void_p()
+        _ok(lib().lre_batch_plan(ctypes.c_void_p(context(dev.index)), arr, len(self.n), self.flags,
+                                 ctypes.byref(h)), "lre_batch_plan")
+        self._h = h.value
+        self._ws = None
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(lib().lre_batch_workspace_bytes(ctypes.c_void_p(self._h)))
+
+    def workspace(self):
+        if self._ws is None or self._ws.numel() < self.workspace_bytes:
+            self._ws = torch.empty(max(1, self.workspace_bytes), dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def run(self, check: bool = False):
+        ws = self.workspace()
+        _ok(lib().lre_batch_run(ctypes.c_void_p(self._h), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                ctypes.c_void_p(_stream(self.device))), "lre_batch_run")
+        if check:
+            check_flags(self.device)
+        return self.coefs, self.rhos
+
+    def tune(self, reps: int = 3) -> float:
+        ws = self.workspace()
+        best = ctypes.c_double()
+        _ok(lib().lre_batch_tune(ctypes.c_void_p(self._h), ctypes.c_void_p(ws.data_ptr()), ws.numel(), int(reps),
+                                 ctypes.byref(best), ctypes.c_void_p(_stream(self.device))), "lre_batch_tune")
+        return best.value
+
+    @property
+    def tiles(self) -> dict:
+        t = lre_batch_tiles()
+        k = ctypes.c_int()
+        _ok(lib().lre_batch_get_tiles(ctypes.c_void_p(self._h), ctypes.byref(t), ctypes.byref(k)),
+            "lre_batch_get_tiles")
+        return {"workers_per_cu": t.workers_per_cu, "counts_tiles": t.counts_tiles, "fold_cols": t.fold_cols,
+                "rho_blocks": t.rho_blocks, "interleave": t.interleave, "items": k.value}
+
+    def set_tiles(self, workers_per_cu, counts_tiles, fold_cols, rho_blocks, interleave):
+        t = lre_batch_tiles(workers_per_cu, counts_tiles, fold_cols, rho_blocks, interleave)
+        _ok(lib().lre_batch_set_tiles(ctypes.c_void_p(self._h), ctypes.byref(t)), "lre_batch_set_tiles")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().lre_batch_destroy(ctypes.c_void_p(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

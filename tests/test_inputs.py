@@ -65,3 +65,15 @@ def test_philox_c_twin_matches_numpy_twin():
     ref = ti.philox_counts_rows(14, 987654321, bases)
     np.testing.assert_array_equal(c, ref)
     np.testing.assert_array_equal(nb, ref.sum(axis=1))
+
+
+def test_device_rotated_amplitudes_match_numpy():
+    """The torch mode-product form of the Born amplitudes equals the numpy one (CPU)."""
+    torch = pytest.importorskip("torch")
+    import tomo_inputs.gpu as tg
+    rng = np.random.default_rng(77)
+    for n in (1, 3, 5):
+        psi = ti.haar_state(n, rng)
+        a = ti.rotated_amplitudes(n, psi)
+        b = tg.rotated_amplitudes(n, torch.from_numpy(psi)).numpy()
+        np.testing.assert_allclose(b, a, rtol=0, atol=1e-14)

@@ -76,3 +76,48 @@ def ghz_multinomial_counts(n: int, p_dep: float, shots: int, seed: int, device="
         out[b0:b1] = cnt.to(torch.uint16)
         del a0, a1, p, idx, cnt
     return out
+
+
+def rotated_amplitudes(n: int, psi: torch.Tensor) -> torch.Tensor:
+    """(U_b psi)_s for every basis b: complex128 [3^n, 2^n] on psi's device (the same
+    axis-by-axis contraction as tomo_inputs.rotated_amplitudes)."""
+    from . import BASIS_BRAS
+    U = torch.from_numpy(BASIS_BRAS).to(psi.device)                    # (3, 2, 2)
+    t = psi.reshape((1,) + (2,) * n).contiguous()
+    for k in range(n):
+        t = torch.tensordot(U, t, dims=([2], [1 + k]))                 # (3, 2, 3^k, rest)
+        t = torch.movedim(t, 2, 0)                                     # (3^k, 3, 2, rest)
+        t = torch.movedim(t, 2, 2 + k)
+        t = t.reshape((-1,) + tuple(t.shape[2:])).contiguous()
+    return t.reshape(3 ** n, 2 ** n)
+
+
+def multinomial_rows(p: torch.Tensor, shots: int, generator: torch.Generator, slab: int = 2048) -> torch.Tensor:
+    """One multinomial draw of `shots` per row of p (rows need not be normalised), as
+    uint16 counts, sampled with torch.multinomial slab by slab."""
+    if shots > 65535:
+        raise ValueError("shots must fit uint16 counts")
+    B, d = p.shape
+    out = torch.empty((B, d), dtype=torch.uint16, device=p.device)
+    for b0 in range(0, B, slab):
+        b1 = min(B, b0 + slab)
+        idx = torch.multinomial(p[b0:b1], shots, replacement=True, generator=generator)
+        cnt = torch.zeros((b1 - b0, d), dtype=torch.int32, device=p.device)
+        cnt.scatter_add_(1, idx, torch.ones_like(idx, dtype=torch.int32))
+        out[b0:b1] = cnt.to(torch.uint16)
+        del idx, cnt
+    return out
+
+
+def haar_multinomial_counts(n: int, shots: int, seed: int, device="cuda") -> torch.Tensor:
+    """Counts of a Haar-random pure state: the state from numpy default_rng(seed)
+    (tomo_inputs.haar_state), Born probabilities of every basis on the device, then
+    `shots` multinomial draws per basis from a torch.Generator seeded with `seed`.
+    uint16 [3^n, 2^n]."""
+    import numpy as np
+    from . import haar_state
+    psi = torch.from_numpy(haar_state(n, np.random.default_rng(seed))).to(device)
+    p = rotated_amplitudes(n, psi).abs() ** 2
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    return multinomial_rows(p, shots, g)
