@@ -41,7 +41,7 @@ struct Plan {
   int F[8] = {0};
   Ty tout[8] = {Ty::U32};
   int J = 0;                 // low step-(ii) qubits
-  size_t off_a = 0, off_b = 0, off_rowpart = 0, off_nb = 0, off_tmp = 0, total = 0;
+  size_t off_a = 0, off_b = 0, off_rowpart = 0, off_nb = 0, off_inv = 0, off_tmp = 0, total = 0;
 };
 
 // Partial sums after folding f qubits are bounded by 3^f * (basis total).
@@ -109,6 +109,7 @@ bool make_plan(int n, uint64_t shots, uint32_t flags, Plan& P) {
   P.off_b = off; off += align256(sizeB);
   P.off_rowpart = off; off += align256(rowpart);
   P.off_nb = off; off += align256(nbytes);
+  P.off_inv = off; off += align256(P.per_basis ? (size_t)ipow3(n) * 8 : 0);
   if (tmp && tmp <= sizeA) P.off_tmp = P.off_a;        // partials are dead by then
   else if (tmp && tmp <= sizeB) P.off_tmp = P.off_b;
   else { P.off_tmp = off; off += align256(tmp); }
@@ -121,7 +122,8 @@ bool make_plan(int n, uint64_t shots, uint32_t flags, Plan& P) {
 struct Fold1Args {
   const uint16_t* counts;
   int n, chunks;
-  const uint32_t* nb;
+  const uint32_t* nb;   // per-basis totals (MFMA kernel)
+  const double* inv;    // their reciprocals (streaming kernel)
   void* out;
   uint32_t* rowpart;
   uint64_t shots;
@@ -152,7 +154,7 @@ void launch_fold1(const Fold1Args& a) {
   constexpr int TH = fold1_threads<Q>();
   static_assert(TH <= 1024 && (TH % StreamGeom<Q>::LPC) == 0, "counts-pass block shape");
   hipLaunchKernelGGL((fold_counts_stream_kernel<Q, TH, Acc, PB, M, MAD24, fold1_minwaves<Q, Acc>()>), dim3((unsigned)a.blocks), dim3(TH), 0,
-                     a.st, a.counts, a.n, a.chunks, a.nb, a.out, a.rowpart, a.shots);
+                     a.st, a.counts, a.n, a.chunks, a.inv, a.out, a.rowpart, a.shots);
 }
 
 // The lane butterflies of 32-bit sums use a 24-bit multiply-add when every value they
@@ -317,8 +319,13 @@ lre_status run_step1(lre_ctx* ctx, const Plan& P, const uint16_t* counts, uint64
     nb = nbd;
   }
   uint32_t* rowpart = reinterpret_cast<uint32_t*>(ws + P.off_rowpart);
+  double* inv = nullptr;
+  if (P.per_basis) {
+    inv = reinterpret_cast<double*>(ws + P.off_inv);
+    hipLaunchKernelGGL(reciprocal_kernel, dim3((unsigned)((nbases + 255) / 256)), dim3(256), 0, st, nb, inv, nbases);
+  }
 
-  Fold1Args a1{counts, n, P.chunks, nb, nullptr, rowpart, shots, P.blocks1, st};
+  Fold1Args a1{counts, n, P.chunks, nb, inv, nullptr, rowpart, shots, P.blocks1, st};
   const bool single = P.npass == 0;
   a1.out = single ? final_out : (void*)(ws + P.off_a);
   const bool ok = (mfma && P.q1 == 7) ? fold1_mfma(P.t1, P.per_basis, single ? fm : Out::Partial, a1)

@@ -360,7 +360,7 @@ __device__ __forceinline__ uint32_t stream_slot(uint32_t a) {
 // block calls this (it synchronises the block).
 template <int Q, int THREADS, typename Acc, bool PER_BASIS, Out MODE, bool MAD24>
 __device__ __forceinline__ void counts_block(const uint16_t* __restrict__ counts, int n, int chunks,
-                                             const uint32_t* __restrict__ nb, void* __restrict__ out,
+                                             const double* __restrict__ inv_nb, void* __restrict__ out,
                                              uint32_t* __restrict__ rowpart, uint64_t shots, int64_t blk,
                                              int tid, Acc* __restrict__ acc, uint32_t* __restrict__ rs_acc) {
   using G = StreamGeom<Q>;
@@ -383,110 +383,161 @@ __device__ __forceinline__ void counts_block(const uint16_t* __restrict__ counts
   for (int i = tid; i < G::NROWS; i += THREADS) rs_acc[i] = 0;
   __syncthreads();
 
+  // Letters of the lane qubits for this lane's (relabelled) Walsh index in row-set rs:
+  // the low bits of the LDS slot.
+  auto ulane_of = [&](int rs) __attribute__((always_inline)) {
+    uint32_t u = 0;
+    int t = rs;
+#pragma unroll
+    for (int j = 0; j < G::LL; ++j) {
+      if ((lw >> j) & 1) u += (uint32_t)(t % 3 + 1) << (2 * j);
+      t /= 3;
+    }
+    return u;
+  };
+
   for (int c = 0; c < chunks; ++c) {
     const int64_t s_hi = s_hi0 + c;
-    for (int rs = grp; rs < G::NRS; rs += GROUPS) {
-      // Letters of the lane qubits for this lane's (relabelled) Walsh index: slot low bits.
-      uint32_t ulane = 0;
-      {
-        int t = rs;
+    const uint16_t* __restrict__ cchunk = counts + row0 * rowlen + (s_hi << Q) + lam * G::V;
+    if constexpr (LB == 3) {
+      // A step is 9 rows (basis digits d0, d1 of qubits 0, 1) at fixed d2 of row-set rs;
+      // a group walks steps (rs, 0), (rs, 1), (rs, 2), (rs + GROUPS, 0), ...
+      constexpr bool PREFETCH = PER_BASIS;   // binary64 path: latency-bound without it
+      Acc L1[4][2], L2[4][4];
 #pragma unroll
-        for (int j = 0; j < G::LL; ++j) {
-          if ((lw >> j) & 1) ulane += (uint32_t)(t % 3 + 1) << (2 * j);
-          t /= 3;
-        }
-      }
-      const int64_t rowb = row0 + (int64_t)rs * G::NSEQ;
-      const uint16_t* __restrict__ cbase = counts + rowb * rowlen + (s_hi << Q) + lam * G::V;
-
-      // Emission of a value whose register-qubit letters are `areg` (4^LB code).
+      for (int a = 0; a < 4; ++a) { L1[a][0] = L1[a][1] = Acc(0); L2[a][0] = L2[a][1] = L2[a][2] = L2[a][3] = Acc(0); }
+      uint32_t ulane = 0;
       auto emit = [&](Acc v, uint32_t areg) __attribute__((always_inline)) {
         wht_lanes1<G::LL, MAD24>(v, sg);
         atomicAdd(&acc[stream_slot_of<Q, LB>(areg, ulane)], v);
       };
-
-      if constexpr (LB == 3) {
-        Acc L1[4][2], L2[4][4];
+      auto load9 = [&](uint32_t (&buf)[9][4], double& invr, int rs, int d2) __attribute__((always_inline)) {
+        const int rr = rs * G::NSEQ + 9 * d2;
+        const uint16_t* __restrict__ p = cchunk + (int64_t)rr * rowlen;
 #pragma unroll
-        for (int a = 0; a < 4; ++a) { L1[a][0] = L1[a][1] = Acc(0); L2[a][0] = L2[a][1] = L2[a][2] = L2[a][3] = Acc(0); }
-#pragma unroll 1
-        for (int d2 = 0; d2 < 3; ++d2) {
-          uint32_t raw[9][4];
+        for (int r = 0; r < 9; ++r) load_raw<8>(p + (int64_t)r * rowlen, buf[r]);
+        if constexpr (PER_BASIS && G::LPC >= 9) invr = inv_nb[row0 + rr + (lam < 9 ? lam : 0)];  // lane r: row r
+      };
+      auto step = [&](const uint32_t (&raw)[9][4], double invr, int rs, int d2) __attribute__((always_inline)) {
+        if (d2 == 0) ulane = ulane_of(rs);
+        const int rr = rs * G::NSEQ + 9 * d2;
+        StaticFor<0, 3>::run([&](auto d1c) __attribute__((always_inline)) {
+          constexpr int d1 = decltype(d1c)::value;
+          Acc L0[4] = {Acc(0), Acc(0), Acc(0), Acc(0)};
+          StaticFor<0, 3>::run([&](auto d0c) __attribute__((always_inline)) {
+            constexpr int d0 = decltype(d0c)::value;
+            constexpr int r = 3 * d1 + d0;
+            int32_t x[8];
+            unpack_raw<8>(raw[r], x);
+            wht_regs<3>(x);
+            const uint32_t tot = lane_sum<G::LL>((uint32_t)x[0]);
+            if (lam == 0) atomicAdd(&rs_acc[rr + r], tot);
+            Acc y[8];
+            if constexpr (PER_BASIS) {
+              // 1/N_b of row r: held by lane r of the group (16 lanes), else loaded here.
+              double inv;
+              if constexpr (G::LPC >= 9) inv = __shfl(invr, (tid & 63 & ~(G::LPC - 1)) + r, 64);
+              else inv = inv_nb[row0 + rr + r];
 #pragma unroll
-          for (int r = 0; r < 9; ++r) load_raw<8>(cbase + (int64_t)(9 * d2 + r) * rowlen, raw[r]);
-          StaticFor<0, 3>::run([&](auto d1c) __attribute__((always_inline)) {
-            constexpr int d1 = decltype(d1c)::value;
-            Acc L0[4] = {Acc(0), Acc(0), Acc(0), Acc(0)};
-            StaticFor<0, 3>::run([&](auto d0c) __attribute__((always_inline)) {
-              constexpr int d0 = decltype(d0c)::value;
-              constexpr int r = 3 * d1 + d0;
-              int32_t x[8];
-              unpack_raw<8>(raw[r], x);
-              wht_regs<3>(x);
-              const uint32_t tot = lane_sum<G::LL>((uint32_t)x[0]);
-              if (lam == 0) atomicAdd(&rs_acc[rs * G::NSEQ + 9 * d2 + r], tot);
-              Acc y[8];
-              if constexpr (PER_BASIS) {
-                const uint32_t N = nb[rowb + 9 * d2 + r];
-                const double inv = N ? 1.0 / (double)N : 0.0;  // empty basis: flagged by the row check
+              for (int v = 0; v < 8; ++v) y[v] = (double)x[v] * inv;
+            } else {
 #pragma unroll
-                for (int v = 0; v < 8; ++v) y[v] = (double)x[v] * inv;
-              } else {
-#pragma unroll
-                for (int v = 0; v < 8; ++v) y[v] = to_acc<Acc>(x[v]);
-              }
-              // y[v], v = m0 + 2 m1 + 4 m2.  Qubit 0: m0 = 0 -> identity (L0); m0 = 1 -> letter d0+1.
-#pragma unroll
-              for (int mr = 0; mr < 4; ++mr) {
-                L0[mr] += y[2 * mr];
-                const Acc w = y[2 * mr + 1];
-                const int m1 = mr & 1, m2 = mr >> 1;
-                if (m1 == 0) {
-                  L1[d0 + 1][m2] += w;
-                } else if (m2 == 0) {
-                  L2[d0 + 1][d1 + 1] += w;
-                } else {
-                  emit(w, (uint32_t)((d0 + 1) + 4 * (d1 + 1) + 16 * (d2 + 1)));
-                }
-              }
-            });
-            // End of the qubit-0 walk: its identity sums move up (letter I at qubit 0).
+              for (int v = 0; v < 8; ++v) y[v] = to_acc<Acc>(x[v]);
+            }
+            // y[v], v = m0 + 2 m1 + 4 m2.  Qubit 0: m0 = 0 -> identity (L0); m0 = 1 -> letter d0+1.
 #pragma unroll
             for (int mr = 0; mr < 4; ++mr) {
+              L0[mr] += y[2 * mr];
+              const Acc w = y[2 * mr + 1];
               const int m1 = mr & 1, m2 = mr >> 1;
-              if (m1 == 0) L1[0][m2] += L0[mr];
-              else if (m2 == 0) L2[0][d1 + 1] += L0[mr];
-              else emit(L0[mr], (uint32_t)(4 * (d1 + 1) + 16 * (d2 + 1)));
+              if (m1 == 0) {
+                L1[d0 + 1][m2] += w;
+              } else if (m2 == 0) {
+                L2[d0 + 1][d1 + 1] += w;
+              } else {
+                emit(w, (uint32_t)((d0 + 1) + 4 * (d1 + 1) + 16 * (d2 + 1)));
+              }
             }
           });
-          // End of the qubit-1 walk (letters of qubit 1 now final).
+          // End of the qubit-0 walk: its identity sums move up (letter I at qubit 0).
 #pragma unroll
-          for (int a0 = 0; a0 < 4; ++a0) {
-            L2[a0][0] += L1[a0][0];
-            emit(L1[a0][1], (uint32_t)(a0 + 16 * (d2 + 1)));
-            L1[a0][0] = L1[a0][1] = Acc(0);
+          for (int mr = 0; mr < 4; ++mr) {
+            const int m1 = mr & 1, m2 = mr >> 1;
+            if (m1 == 0) L1[0][m2] += L0[mr];
+            else if (m2 == 0) L2[0][d1 + 1] += L0[mr];
+            else emit(L0[mr], (uint32_t)(4 * (d1 + 1) + 16 * (d2 + 1)));
+          }
+        });
+        // End of the qubit-1 walk (letters of qubit 1 now final).
+#pragma unroll
+        for (int a0 = 0; a0 < 4; ++a0) {
+          L2[a0][0] += L1[a0][0];
+          emit(L1[a0][1], (uint32_t)(a0 + 16 * (d2 + 1)));
+          L1[a0][0] = L1[a0][1] = Acc(0);
+        }
+        if (d2 == 2) {
+          // End of the qubit-2 walk: identity letter at qubit 2.
+#pragma unroll
+          for (int a0 = 0; a0 < 4; ++a0)
+#pragma unroll
+            for (int a1 = 0; a1 < 4; ++a1) {
+              emit(L2[a0][a1], (uint32_t)(a0 + 4 * a1));
+              L2[a0][a1] = Acc(0);
+            }
+        }
+      };
+      if constexpr (PREFETCH) {
+        // Double-buffered: the next step's rows are in flight while this one is folded.
+        uint32_t bufA[9][4], bufB[9][4];
+        double invA = 0.0, invB = 0.0;
+        // The prefetch is unconditional (past the last step it re-reads the current rows)
+        // so that the wait for the current buffer never has to cover it.
+        int rs = grp, d2 = 0;
+        if (rs < G::NRS) {
+          load9(bufA, invA, rs, 0);
+          for (;;) {
+            int rs1 = d2 == 2 ? rs + GROUPS : rs, d21 = d2 == 2 ? 0 : d2 + 1;
+            bool more = rs1 < G::NRS;
+            load9(bufB, invB, more ? rs1 : rs, more ? d21 : d2);
+            step(bufA, invA, rs, d2);
+            if (!more) break;
+            rs = rs1;
+            d2 = d21;
+            rs1 = d2 == 2 ? rs + GROUPS : rs;
+            d21 = d2 == 2 ? 0 : d2 + 1;
+            more = rs1 < G::NRS;
+            load9(bufA, invA, more ? rs1 : rs, more ? d21 : d2);
+            step(bufB, invB, rs, d2);
+            if (!more) break;
+            rs = rs1;
+            d2 = d21;
           }
         }
-        // End of the qubit-2 walk: identity letter at qubit 2.
-#pragma unroll
-        for (int a0 = 0; a0 < 4; ++a0)
-#pragma unroll
-          for (int a1 = 0; a1 < 4; ++a1) emit(L2[a0][a1], (uint32_t)(a0 + 4 * a1));
       } else {
-        // Small tiles (Q < 3): one lane holds a whole row (LPC = 1); plain direct fold.
-        static_assert(G::LPC == 1, "small-tile path expects one lane per row");
+        for (int rs = grp; rs < G::NRS; rs += GROUPS) {
+#pragma unroll 1
+          for (int d2 = 0; d2 < 3; ++d2) {
+            uint32_t raw[9][4];
+            double invr = 0.0;
+            load9(raw, invr, rs, d2);
+            step(raw, invr, rs, d2);
+          }
+        }
+      }
+    } else {
+      // Small tiles (Q < 3): one lane holds a whole row (LPC = 1); plain direct fold.
+      static_assert(G::LPC == 1, "small-tile path expects one lane per row");
+      for (int rs = grp; rs < G::NRS; rs += GROUPS) {
+        const int64_t rowb = row0 + (int64_t)rs * G::NSEQ;
         for (int r = 0; r < G::NSEQ; ++r) {
           uint32_t raw[G::V / 2];
-          load_raw<G::V>(cbase + (int64_t)r * rowlen, raw);
+          load_raw<G::V>(cchunk + (int64_t)(rs * G::NSEQ + r) * rowlen, raw);
           int32_t x[G::V];
           unpack_raw<G::V>(raw, x);
           wht_regs<LB>(x);
           atomicAdd(&rs_acc[rs * G::NSEQ + r], (uint32_t)x[0]);
           double inv = 1.0;
-          if constexpr (PER_BASIS) {
-            const uint32_t N = nb[rowb + r];
-            inv = N ? 1.0 / (double)N : 0.0;
-          }
+          if constexpr (PER_BASIS) inv = inv_nb[rowb + r];
 #pragma unroll
           for (int m = 0; m < G::V; ++m) {
             uint32_t areg = 0;
@@ -531,11 +582,11 @@ __device__ __forceinline__ void counts_block(const uint16_t* __restrict__ counts
 
 template <int Q, int THREADS, typename Acc, bool PER_BASIS, Out MODE, bool MAD24, int MINWAVES = 1>
 __global__ __launch_bounds__(THREADS, MINWAVES) void fold_counts_stream_kernel(
-    const uint16_t* __restrict__ counts, int n, int chunks, const uint32_t* __restrict__ nb,
+    const uint16_t* __restrict__ counts, int n, int chunks, const double* __restrict__ inv_nb,
     void* __restrict__ out, uint32_t* __restrict__ rowpart, uint64_t shots) {
   __shared__ Acc acc[StreamGeom<Q>::NACC];
   __shared__ uint32_t rs_acc[StreamGeom<Q>::NROWS];
-  counts_block<Q, THREADS, Acc, PER_BASIS, MODE, MAD24>(counts, n, chunks, nb, out, rowpart, shots,
+  counts_block<Q, THREADS, Acc, PER_BASIS, MODE, MAD24>(counts, n, chunks, inv_nb, out, rowpart, shots,
                                                        blockIdx.x, threadIdx.x, acc, rs_acc);
 }
 
@@ -849,6 +900,12 @@ static __global__ __launch_bounds__(256) void row_totals_kernel(const uint16_t* 
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
   __syncthreads();
   if (threadIdx.x == 0) nb[b] = part[0] + part[1] + part[2] + part[3];
+}
+
+// inv[b] = 1 / N_b (0 for an empty basis, which the row check flags), correctly rounded.
+static __global__ void reciprocal_kernel(const uint32_t* __restrict__ nb, double* __restrict__ inv, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < count) inv[i] = nb[i] ? 1.0 / (double)nb[i] : 0.0;
 }
 
 // rowpart as written by fold_counts_kernel: [3^n / rows][runs][rows].
