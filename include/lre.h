@@ -139,9 +139,9 @@ lre_status lre_signed_sums(lre_ctx* ctx, int n, const uint16_t* counts, const in
  * lre_estimate returns for it (steps (i) and (ii), Sec. II eqs. 3-4): the same
  * kernels' arithmetic, bit-identical coefficients and rho.
  *
- * lre_batch_plan builds a work list (the counts-pass tiles, later passes, row checks
- * and step-(ii) blocks of every instance, in dependency order, split into work items)
- * and uploads it.  lre_batch_run enqueues two kernels: a fill kernel that clears the
+ * lre_batch_plan builds a work list (an instance of n <= 7 qubits is one item; a larger
+ * one is split into its counts-pass tiles, row check, later pass and step-(ii) blocks,
+ * in dependency order) and uploads it.  lre_batch_run enqueues two kernels: a fill kernel that clears the
  * item and dependency counters in the workspace, then one persistent kernel whose
  * workgroups take items from the list in order; an item that needs the results of
  * earlier items waits for their counters (a bounded wait: on expiry the item is
@@ -166,7 +166,8 @@ typedef struct {
   int workers_per_cu;   /* persistent workgroups per compute unit: 1 or 2 */
   int counts_tiles;     /* counts-pass tiles (3^7 rows x 128 outcomes) per item, >= 1 */
   int fold_cols;        /* later-pass columns per item, multiple of 432 */
-  int rho_blocks;       /* step-(ii) blocks per item, >= 1 */
+  int rho_blocks;       /* step-(ii) work per item, >= 1: high-qubit row patterns x_hi
+                           (2^(n-6) per instance of n > 7 qubits) */
   int interleave;       /* 0: stage by stage, largest instances first;
                            1: instance by instance (all stages of an instance together) */
 } lre_batch_tiles;
@@ -192,7 +193,7 @@ lre_status lre_batch_set_tiles(lre_batch* plan, const lre_batch_tiles* tiles);
 /* The plan's current work-item shape and work-item count. */
 lre_status lre_batch_get_tiles(const lre_batch* plan, lre_batch_tiles* tiles, int* num_items);
 
-/* Autotuner: runs the batch (lre_batch_run) for each candidate work-item shape,
+/* Autotuner: runs the batch (lre_batch_run) for each of 72 candidate work-item shapes,
  * `reps` timed runs each after one warm-up, keeps the fastest shape and returns its
  * mean time in *best_ms (may be NULL).  Synchronous on `stream`; overwrites the
  * instances' outputs.  workspace as for lre_batch_run. */

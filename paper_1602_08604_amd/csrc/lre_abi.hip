@@ -24,6 +24,7 @@ constexpr int kMaxFLast = 2;  // qubits folded by the final pass
 constexpr int kRhoJ = 6;      // qubits of the low step-(ii) transform
 constexpr int kRhoXB = 8;     // row entries per block in the high step-(ii) transform
 constexpr int kRhoHMax = LRE_MAX_QUBITS - kRhoJ;
+constexpr int kRhoRegH = 4;   // high step-(ii) qubits transformed in registers (n <= 10)
 
 enum class Ty : int { U32 = 0, F64 = 1 };
 
@@ -300,6 +301,18 @@ void launch_rho(const Plan& P, const double* coef, void* rho, char* ws, hipStrea
   hipLaunchKernelGGL((rho_low_kernel<kRhoJ, false, OutT>), dim3((unsigned)ipow4(n - kRhoJ)), dim3(256), 0, st,
                      coef, (void*)tmp, n);
   const int64_t D = (int64_t)1 << kRhoJ;
+  if (n - kRhoJ <= kRhoRegH) {
+    // few high qubits: one thread per (x_hi, r_lo, x_lo), transform in registers
+    const int64_t count = ((int64_t)1 << (n - kRhoJ)) * D * D;
+    const dim3 grid((unsigned)((count + 255) / 256));
+    switch (n - kRhoJ) {
+      case 1: hipLaunchKernelGGL((rho_high_reg_kernel<1, OutT>), grid, dim3(256), 0, st, (const double2*)tmp, rho, n, (int)kRhoJ, count); break;
+      case 2: hipLaunchKernelGGL((rho_high_reg_kernel<2, OutT>), grid, dim3(256), 0, st, (const double2*)tmp, rho, n, (int)kRhoJ, count); break;
+      case 3: hipLaunchKernelGGL((rho_high_reg_kernel<3, OutT>), grid, dim3(256), 0, st, (const double2*)tmp, rho, n, (int)kRhoJ, count); break;
+      default: hipLaunchKernelGGL((rho_high_reg_kernel<4, OutT>), grid, dim3(256), 0, st, (const double2*)tmp, rho, n, (int)kRhoJ, count); break;
+    }
+    return;
+  }
   const int64_t blocks = ((int64_t)1 << (n - kRhoJ)) * D * (D / kRhoXB);
   hipLaunchKernelGGL((rho_high_kernel<kRhoXB, kRhoHMax, OutT>), dim3((unsigned)blocks), dim3(256), 0, st,
                      (const double2*)tmp, rho, n, (int)kRhoJ);

@@ -1,16 +1,19 @@
 // lre_batch.hip -- batched estimation (lre_batch_* in include/lre.h): many independent
 // instances of steps (i) and (ii) in one persistent kernel driven by a work list.
 //
-// The work of an instance is the same sequence of blocks the single-instance launches
-// run (lre_kernels.hpp): counts-pass tiles, the later fold pass (n > 7), the row-total
-// check, the low and high step-(ii) transforms.  The host cuts every stage into work
-// items (ranges of those blocks), orders them so that an item only ever depends on
-// items listed before it, and uploads the list.  Each persistent workgroup takes the
-// next item (one atomic counter), waits until the items it depends on have finished
-// (per-instance, per-stage completion counters), runs it and bumps its own stage's
-// counter.  Because items are taken in list order by running workgroups, every item
-// an item waits for has already been taken by a running workgroup, so every wait ends;
-// the wait is bounded anyway (FLAG_WAIT) so that no wave can spin forever.
+// An instance of at most 7 qubits is one counts-pass tile: one work item runs it from
+// the counts to rho inside one workgroup (the phases ordered by workgroup barriers).
+// A larger instance is cut into items per stage -- counts-pass tiles, the row-total
+// check, the later fold pass, step (ii) per group of x_hi row patterns --
+// the same per-block device functions the single-instance kernels run
+// (lre_kernels.hpp).  The host lists the items so that an item only ever depends on
+// items listed before it.  Each persistent workgroup takes the next item (one atomic
+// counter), waits until the items it depends on have finished (per-instance, per-stage
+// completion counters, agent-scope acquire), runs it and, when a later item consumes
+// its output, releases it and bumps its stage's counter.  Items are taken in list
+// order by running workgroups, so every item waited for has already been taken by a
+// running workgroup and every wait ends; the wait is bounded anyway (FLAG_WAIT) so
+// that no wave can spin forever.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -33,12 +36,11 @@ namespace {
 constexpr int kBT = 432;          // threads of a persistent workgroup (27 row groups of 16 lanes)
 constexpr int kQ = 7;             // counts-pass tile qubits (n >= 7)
 constexpr int kJ = 6;             // low step-(ii) qubits (n > 6)
-constexpr int kXB = 64;           // step-(ii) high transform: row entries per block
 constexpr uint32_t kWaitLimit = 1u << 24;  // sleeps of ~64 clocks before a wait gives up
 
-enum Kind : uint8_t { K_COUNTS = 0, K_CHECK = 1, K_FOLD = 2, K_RHO_LOW = 3, K_RHO_HIGH = 4 };
+enum Kind : uint8_t { K_SMALL = 0, K_COUNTS = 1, K_CHECK = 2, K_FOLD = 3, K_RHO = 4 };
 // variant bits
-enum : uint8_t { V_FINAL = 8, V_MAD24 = 16, V_FP32 = 32 };
+enum : uint8_t { V_MAD24 = 16, V_FP32 = 32, V_RHO = 64 };
 
 struct BItem {
   int32_t inst;
@@ -47,7 +49,7 @@ struct BItem {
   uint32_t wait_target;  // value it must reach
   int32_t done_ctr;      // counter to increment when done (-1: none)
   int32_t pad2;
-  int64_t begin, end;    // block / column / basis range
+  int64_t begin, end;    // block / column / basis / element range
 };
 
 struct BInst {
@@ -62,114 +64,135 @@ struct BInst {
 constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
 constexpr size_t kLdsCounts = (size_t)StreamGeom<kQ>::NACC * 4 + (size_t)StreamGeom<kQ>::NROWS * 4;
 constexpr size_t kLdsRhoLow = 2 * (size_t)RhoLowLds<kJ>::SIZE * 8;
-constexpr size_t kLdsRhoHigh = 2 * (size_t)kXB * ((1 << (LRE_BATCH_MAX_QUBITS - kJ)) + 1) * 8;
-constexpr size_t kLds = cmax(kLdsCounts, cmax(kLdsRhoLow, kLdsRhoHigh));
+constexpr size_t kLds = cmax(kLdsCounts, kLdsRhoLow);
+constexpr int64_t kRhoElemsPerBlock = 4096;  // step-(ii) high elements per unit of rho_blocks
 
-template <int Q, bool FINAL, bool MAD24>
-__device__ __noinline__ void run_counts_v(const BInst& I, int64_t b0, int64_t b1, int tid, char* ws, char* smem) {
+template <typename OutT>
+__device__ __forceinline__ void rho_high_range(const BInst& I, int64_t e0, int64_t e1, int tid, char* ws) {
+  const double2* tmp = reinterpret_cast<const double2*>(ws + I.off_tmp);
+  switch (I.n - kJ) {
+    case 1: for (int64_t t = e0 + tid; t < e1; t += kBT) rho_high_reg<1, OutT>(tmp, I.rho, I.n, kJ, t); break;
+    case 2: for (int64_t t = e0 + tid; t < e1; t += kBT) rho_high_reg<2, OutT>(tmp, I.rho, I.n, kJ, t); break;
+    default: for (int64_t t = e0 + tid; t < e1; t += kBT) rho_high_reg<3, OutT>(tmp, I.rho, I.n, kJ, t); break;
+  }
+}
+
+// An instance with n <= 7 (one counts-pass tile) from counts to rho in one workgroup;
+// __syncthreads orders the phases (it is a workgroup-scope release/acquire).
+template <int Q, bool MAD24, bool PREFETCH, typename OutT>
+__device__ __forceinline__ void small_rho(const BInst& I, int tid, char* ws, double* re, double* im) {
+  if constexpr (Q <= kJ) {
+    rho_low_block<Q, true, OutT, kBT>(I.coef, I.rho, I.n, 0, tid, re, im);
+  } else {
+    for (int64_t a = 0; a < 4; ++a) {
+      rho_low_block<kJ, false, OutT, kBT>(I.coef, ws + I.off_tmp, I.n, a, tid, re, im);
+      __syncthreads();
+    }
+    rho_high_range<OutT>(I, 0, (int64_t)2 * 64 * 64, tid, ws);
+  }
+}
+
+template <int Q, bool MAD24, bool PREFETCH>
+__device__ __noinline__ void run_small(const BInst& I, uint8_t var, int tid, char* ws, char* smem,
+                                       uint32_t* flags) {
   uint32_t* acc = reinterpret_cast<uint32_t*>(smem);
   uint32_t* rs = acc + StreamGeom<Q>::NACC;
   uint32_t* rowpart = reinterpret_cast<uint32_t*>(ws + I.off_rowpart);
-  void* out = FINAL ? (void*)I.coef : (void*)(ws + I.off_part);
-  constexpr Out M = FINAL ? Out::CoefUniform : Out::Partial;
+  counts_block<Q, kBT, uint32_t, false, Out::CoefUniform, MAD24, PREFETCH>(I.counts, I.n, 1, nullptr, I.coef,
+                                                                          rowpart, I.shots, 0, tid, acc, rs);
+  __syncthreads();
+  const int64_t rows = ipow3(Q);
+  for (int64_t b = tid; b < rows; b += kBT) check_row(rowpart, rows, 1, nullptr, I.shots, b, flags);
+  if (var & V_RHO) {
+    double* re = reinterpret_cast<double*>(smem);
+    double* im = re + (kLds / 16);
+    if (var & V_FP32) small_rho<Q, MAD24, PREFETCH, float>(I, tid, ws, re, im);
+    else small_rho<Q, MAD24, PREFETCH, double>(I, tid, ws, re, im);
+  }
+}
+
+template <bool MAD24, bool PREFETCH>
+__device__ __noinline__ void run_counts(const BInst& I, int64_t b0, int64_t b1, int tid, char* ws, char* smem) {
+  uint32_t* acc = reinterpret_cast<uint32_t*>(smem);
+  uint32_t* rs = acc + StreamGeom<kQ>::NACC;
+  uint32_t* rowpart = reinterpret_cast<uint32_t*>(ws + I.off_rowpart);
   for (int64_t blk = b0; blk < b1; ++blk) {
-    counts_block<Q, kBT, uint32_t, false, M, MAD24>(I.counts, I.n, 1, nullptr, out, rowpart, I.shots, blk, tid,
-                                                    acc, rs);
+    counts_block<kQ, kBT, uint32_t, false, Out::Partial, MAD24, PREFETCH>(I.counts, I.n, 1, nullptr, ws + I.off_part,
+                                                                         rowpart, I.shots, blk, tid, acc, rs);
     __syncthreads();  // the next tile clears the LDS this one still reads
   }
 }
 
-// Instances with n < 7 fold everything in one tile (final output, exact negation path).
-__device__ __forceinline__ void run_counts(const BInst& I, uint8_t var, int64_t b0, int64_t b1, int tid, char* ws,
-                                           char* smem) {
-  const bool fin = (var & V_FINAL) != 0, mad = (var & V_MAD24) != 0;
-  switch (var & 7) {
-    case 1: run_counts_v<1, true, false>(I, b0, b1, tid, ws, smem); break;
-    case 2: run_counts_v<2, true, false>(I, b0, b1, tid, ws, smem); break;
-    case 3: run_counts_v<3, true, false>(I, b0, b1, tid, ws, smem); break;
-    case 4: run_counts_v<4, true, false>(I, b0, b1, tid, ws, smem); break;
-    case 5: run_counts_v<5, true, false>(I, b0, b1, tid, ws, smem); break;
-    case 6: run_counts_v<6, true, false>(I, b0, b1, tid, ws, smem); break;
-    default:
-      if (fin) {
-        if (mad) run_counts_v<7, true, true>(I, b0, b1, tid, ws, smem);
-        else run_counts_v<7, true, false>(I, b0, b1, tid, ws, smem);
-      } else {
-        if (mad) run_counts_v<7, false, true>(I, b0, b1, tid, ws, smem);
-        else run_counts_v<7, false, false>(I, b0, b1, tid, ws, smem);
+__device__ __noinline__ void run_fold(const BInst& I, int64_t c0, int64_t c1, int tid, char* ws) {
+  const uint32_t* in = reinterpret_cast<const uint32_t*>(ws + I.off_part);
+  const int h = I.n - kQ;
+  for (int64_t col = c0 + tid; col < c1; col += kBT) {
+    if (h == 1) fold_partial_col<1, uint32_t, uint32_t, Out::CoefUniform>(in, I.coef, I.n, h, kQ, I.shots, col);
+    else fold_partial_col<2, uint32_t, uint32_t, Out::CoefUniform>(in, I.coef, I.n, h, kQ, I.shots, col);
+  }
+}
+
+// Step (ii) for the x_hi values [x0, x1) of an instance with n > 7: the low transform of
+// the 2^H coefficient blocks whose high letters have pattern x_hi (into the
+// intermediate), then the high transform of the 4^6 (r_lo, x_lo) entries of each x_hi
+// row group -- both inside this workgroup, ordered by barriers.
+template <typename OutT>
+__device__ __noinline__ void run_rho(const BInst& I, int64_t x0, int64_t x1, int tid, char* ws, char* smem) {
+  double* re = reinterpret_cast<double*>(smem);
+  double* im = re + (kLds / 16);
+  const int H = I.n - kJ;
+  for (int64_t xh = x0; xh < x1; ++xh) {
+    for (int z = 0; z < (1 << H); ++z) {
+      int64_t a_hi = 0;
+      for (int p = H - 1; p >= 0; --p) {
+        const int xb = (int)(xh >> p) & 1, zb = (z >> p) & 1;
+        a_hi = a_hi * 4 + (xb ? (zb ? 2 : 1) : (zb ? 3 : 0));
       }
+      rho_low_block<kJ, false, OutT, kBT>(I.coef, ws + I.off_tmp, I.n, a_hi, tid, re, im);
+      __syncthreads();
+    }
+    rho_high_range<OutT>(I, xh * kRhoElemsPerBlock, (xh + 1) * kRhoElemsPerBlock, tid, ws);
+  }
+}
+
+template <bool PREFETCH>
+__device__ __forceinline__ void dispatch_small(const BInst& I, uint8_t var, int tid, char* ws, char* smem,
+                                               uint32_t* flags) {
+  switch (I.n) {
+    case 1: run_small<1, false, PREFETCH>(I, var, tid, ws, smem, flags); break;
+    case 2: run_small<2, false, PREFETCH>(I, var, tid, ws, smem, flags); break;
+    case 3: run_small<3, false, PREFETCH>(I, var, tid, ws, smem, flags); break;
+    case 4: run_small<4, false, PREFETCH>(I, var, tid, ws, smem, flags); break;
+    case 5: run_small<5, false, PREFETCH>(I, var, tid, ws, smem, flags); break;
+    case 6: run_small<6, false, PREFETCH>(I, var, tid, ws, smem, flags); break;
+    default:
+      if (var & V_MAD24) run_small<7, true, PREFETCH>(I, var, tid, ws, smem, flags);
+      else run_small<7, false, PREFETCH>(I, var, tid, ws, smem, flags);
       break;
   }
 }
 
-__device__ __noinline__ void run_fold(const BInst& I, uint8_t var, int64_t c0, int64_t c1, int tid, char* ws) {
-  const uint32_t* in = reinterpret_cast<const uint32_t*>(ws + I.off_part);
-  const int h = I.n - kQ;
-  for (int64_t col = c0 + tid; col < c1; col += kBT) {
-    if ((var & 7) == 1)
-      fold_partial_col<1, uint32_t, uint32_t, Out::CoefUniform>(in, I.coef, I.n, h, kQ, I.shots, col);
-    else
-      fold_partial_col<2, uint32_t, uint32_t, Out::CoefUniform>(in, I.coef, I.n, h, kQ, I.shots, col);
-  }
-}
-
-template <int J, typename OutT>
-__device__ __noinline__ void run_rho_low_j(const BInst& I, bool fin, int64_t a0, int64_t a1, int tid, char* ws,
-                                              double* re, double* im) {
-  for (int64_t a = a0; a < a1; ++a) {
-    if constexpr (J == kJ) {
-      if (fin) rho_low_block<J, true, OutT, kBT>(I.coef, I.rho, I.n, a, tid, re, im);
-      else rho_low_block<J, false, OutT, kBT>(I.coef, ws + I.off_tmp, I.n, a, tid, re, im);
-    } else {
-      rho_low_block<J, true, OutT, kBT>(I.coef, I.rho, I.n, a, tid, re, im);
-    }
-    __syncthreads();
-  }
-}
-
-template <typename OutT>
-__device__ __forceinline__ void run_rho_low(const BInst& I, uint8_t var, int64_t a0, int64_t a1, int tid, char* ws,
-                                            double* re, double* im) {
-  const bool fin = (var & V_FINAL) != 0;
-  switch (var & 7) {
-    case 1: run_rho_low_j<1, OutT>(I, fin, a0, a1, tid, ws, re, im); break;
-    case 2: run_rho_low_j<2, OutT>(I, fin, a0, a1, tid, ws, re, im); break;
-    case 3: run_rho_low_j<3, OutT>(I, fin, a0, a1, tid, ws, re, im); break;
-    case 4: run_rho_low_j<4, OutT>(I, fin, a0, a1, tid, ws, re, im); break;
-    case 5: run_rho_low_j<5, OutT>(I, fin, a0, a1, tid, ws, re, im); break;
-    default: run_rho_low_j<6, OutT>(I, fin, a0, a1, tid, ws, re, im); break;
-  }
-}
-
-template <typename OutT>
-__device__ __noinline__ void run_rho_high(const BInst& I, int64_t b0, int64_t b1, int tid, char* ws, double* re,
-                                             double* im) {
-  const double2* tmp = reinterpret_cast<const double2*>(ws + I.off_tmp);
-  for (int64_t b = b0; b < b1; ++b) {
-    rho_high_block<kXB, OutT, kBT>(tmp, I.rho, I.n, kJ, b, tid, re, im);
-    __syncthreads();
-  }
-}
-
 // ctl[0]: next item; ctl[1 + 3 j + k]: completion counter of stage k of instance j.
-__global__ __launch_bounds__(kBT, 4) void batch_kernel(const BItem* __restrict__ items, int nitems,
-                                                      const BInst* __restrict__ insts, char* __restrict__ ws,
-                                                      uint32_t* __restrict__ ctl, uint32_t* __restrict__ flags) {
+// WORKERS: persistent workgroups per CU the launch is shaped for (one: registers for the
+// row prefetch; two: no prefetch, 128 registers).
+template <int WORKERS>
+__global__ __launch_bounds__(kBT, WORKERS == 2 ? 4 : 1) void batch_kernel(
+    const BItem* __restrict__ items, int nitems, const BInst* __restrict__ insts, char* __restrict__ ws,
+    uint32_t* __restrict__ ctl, uint32_t* __restrict__ flags) {
+  constexpr bool PF = WORKERS == 1;
   __shared__ __align__(16) char smem[kLds];
   __shared__ int s_item;
   __shared__ int s_skip;
   const int tid = threadIdx.x;
-  double* re = reinterpret_cast<double*>(smem);
-  double* im = re + (kLds / 16);
   for (;;) {
     if (tid == 0) s_item = (int)atomicAdd(&ctl[0], 1u);
     __syncthreads();
     const int it = s_item;
     if (it >= nitems) break;
     const BItem W = items[it];
-    if (tid == 0) {
-      int skip = 0;
-      if (W.wait_ctr >= 0) {
+    if (W.wait_ctr >= 0) {
+      if (tid == 0) {
+        int skip = 0;
         uint32_t spins = 0;
         while (__hip_atomic_load(&ctl[W.wait_ctr], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < W.wait_target) {
           if (++spins > kWaitLimit) {
@@ -179,39 +202,41 @@ __global__ __launch_bounds__(kBT, 4) void batch_kernel(const BItem* __restrict__
           }
           __builtin_amdgcn_s_sleep(1);
         }
+        s_skip = skip;
       }
-      s_skip = skip;
+      __syncthreads();
+      // Acquire: the producers' results become visible to every thread of this workgroup.
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      if (s_skip) continue;  // uniform: the skipped item's counter never moves, its consumers time out too
     }
-    __syncthreads();
-    // Acquire: the producers' results become visible to every thread of this workgroup.
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    if (!s_skip) {
-      const BInst I = insts[W.inst];
-      switch (W.kind) {
-        case K_COUNTS: run_counts(I, W.variant, W.begin, W.end, tid, ws, smem); break;
-        case K_CHECK: {
-          const int64_t rows = ipow3(I.q1);
-          const int64_t runs = (int64_t)1 << (I.n - I.q1);
-          const uint32_t* rowpart = reinterpret_cast<const uint32_t*>(ws + I.off_rowpart);
-          for (int64_t b = W.begin + tid; b < W.end; b += kBT) check_row(rowpart, rows, runs, nullptr, I.shots, b, flags);
-          break;
-        }
-        case K_FOLD: run_fold(I, W.variant, W.begin, W.end, tid, ws); break;
-        case K_RHO_LOW:
-          if (W.variant & V_FP32) run_rho_low<float>(I, W.variant, W.begin, W.end, tid, ws, re, im);
-          else run_rho_low<double>(I, W.variant, W.begin, W.end, tid, ws, re, im);
-          break;
-        default:
-          if (W.variant & V_FP32) run_rho_high<float>(I, W.begin, W.end, tid, ws, re, im);
-          else run_rho_high<double>(I, W.begin, W.end, tid, ws, re, im);
-          break;
+    const BInst I = insts[W.inst];
+    switch (W.kind) {
+      case K_SMALL: dispatch_small<PF>(I, W.variant, tid, ws, smem, flags); break;
+      case K_COUNTS:
+        if (W.variant & V_MAD24) run_counts<true, PF>(I, W.begin, W.end, tid, ws, smem);
+        else run_counts<false, PF>(I, W.begin, W.end, tid, ws, smem);
+        break;
+      case K_CHECK: {
+        const int64_t rows = ipow3(I.q1);
+        const int64_t runs = (int64_t)1 << (I.n - I.q1);
+        const uint32_t* rowpart = reinterpret_cast<const uint32_t*>(ws + I.off_rowpart);
+        for (int64_t b = W.begin + tid; b < W.end; b += kBT) check_row(rowpart, rows, runs, nullptr, I.shots, b, flags);
+        break;
       }
+      case K_FOLD: run_fold(I, W.begin, W.end, tid, ws); break;
+      default:
+        if (W.variant & V_FP32) run_rho<float>(I, W.begin, W.end, tid, ws, smem);
+        else run_rho<double>(I, W.begin, W.end, tid, ws, smem);
+        break;
     }
-    // Release: this workgroup's results are visible device-wide before the counter moves.
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
-    if (tid == 0 && W.done_ctr >= 0)
-      __hip_atomic_fetch_add(&ctl[W.done_ctr], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (W.done_ctr >= 0) {
+      // Release: this workgroup's results are visible device-wide before the counter moves.
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __syncthreads();
+      if (tid == 0) __hip_atomic_fetch_add(&ctl[W.done_ctr], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      __syncthreads();  // s_item and the LDS are reused by the next item
+    }
   }
 }
 
@@ -270,7 +295,7 @@ void add_range(std::vector<BItem>& out, int inst, Kind kind, uint8_t var, int64_
 
 // Work items of instance j for one stage (0 counts, 1 check + fold, 2 rho low, 3 rho high).
 struct StageCounts {
-  uint32_t counts = 0, fold = 0, rho_low = 0;
+  uint32_t counts = 0, fold = 0;
 };
 
 void emit_stage(const lre_batch& B, int j, int stage, std::vector<BItem>& out, StageCounts& sc) {
@@ -278,39 +303,29 @@ void emit_stage(const lre_batch& B, int j, int stage, std::vector<BItem>& out, S
   const lre_batch_tiles& t = B.tiles;
   const bool want_rho = !(B.flags & LRE_NO_RHO);
   const uint8_t fp32 = (B.flags & LRE_RHO_FP32) ? V_FP32 : 0;
-  const int32_t c_counts = 1 + 3 * j, c_fold = 2 + 3 * j, c_low = 3 + 3 * j;
+  const uint8_t mad = m.mad24 ? V_MAD24 : 0;
+  const int32_t c_counts = 1 + 3 * j, c_fold = 2 + 3 * j;
+  if (m.n <= kQ) {  // one tile: the whole instance is one item
+    if (stage == 0)
+      add_range(out, j, K_SMALL, (uint8_t)(mad | fp32 | (want_rho ? V_RHO : 0)), 1, 1, -1, 0, -1, nullptr);
+    return;
+  }
   switch (stage) {
-    case 0: {
-      const uint8_t var = (uint8_t)(m.q1 | (m.F == 0 ? V_FINAL : 0) | (m.mad24 ? V_MAD24 : 0));
-      add_range(out, j, K_COUNTS, var, m.blocks1, t.counts_tiles, -1, 0, c_counts, &sc.counts);
+    case 0:
+      add_range(out, j, K_COUNTS, mad, m.blocks1, t.counts_tiles, -1, 0, c_counts, &sc.counts);
       break;
-    }
     case 1: {
       const int64_t nb = ipow3(m.n);
-      add_range(out, j, K_CHECK, 0, nb, std::max<int64_t>(nb, 1), c_counts, sc.counts, -1, nullptr);
-      if (m.F > 0) {
-        const int64_t ncols = ipow4(kQ);  // one later pass folds all n - 7 remaining qubits
-        add_range(out, j, K_FOLD, (uint8_t)m.F, ncols, t.fold_cols, c_counts, sc.counts, c_fold, &sc.fold);
-      }
+      add_range(out, j, K_CHECK, 0, nb, nb, c_counts, sc.counts, -1, nullptr);
+      add_range(out, j, K_FOLD, 0, ipow4(kQ), t.fold_cols, c_counts, sc.counts, want_rho ? c_fold : -1, &sc.fold);
       break;
     }
-    case 2: {
-      if (!want_rho) break;
-      const int J = m.n < kJ ? m.n : kJ;
-      const bool fin = m.n <= kJ;
-      const int32_t wc = m.F > 0 ? c_fold : c_counts;
-      const uint32_t wt = m.F > 0 ? sc.fold : sc.counts;
-      add_range(out, j, K_RHO_LOW, (uint8_t)(J | (fin ? V_FINAL : 0) | fp32), ipow4(m.n - J), t.rho_blocks, wc, wt,
-                c_low, &sc.rho_low);
+    case 2:
+      if (want_rho)
+        add_range(out, j, K_RHO, fp32, (int64_t)1 << (m.n - kJ), t.rho_blocks, c_fold, sc.fold, -1, nullptr);
       break;
-    }
-    default: {
-      if (!want_rho || m.n <= kJ) break;
-      const int64_t D = (int64_t)1 << kJ;
-      const int64_t blocks = ((int64_t)1 << (m.n - kJ)) * D * (D / kXB);
-      add_range(out, j, K_RHO_HIGH, fp32, blocks, t.rho_blocks, c_low, sc.rho_low, -1, nullptr);
+    default:
       break;
-    }
   }
 }
 
@@ -421,7 +436,7 @@ lre_status lre_batch_plan(lre_ctx* ctx, const lre_instance* inst, int count, uin
     delete B;
     return LRE_E_HIP;
   }
-  B->tiles = lre_batch_tiles{2, 2, kBT * 8, 8, 0};
+  B->tiles = lre_batch_tiles{1, 4, kBT * 16, 1, 0};
   const lre_status s = rebuild(*B);
   if (s != LRE_OK) {
     lre_batch_destroy(B);
@@ -458,8 +473,12 @@ lre_status lre_batch_run(lre_batch* plan, void* workspace, size_t workspace_byte
   const int64_t words = 1 + 3 * (int64_t)plan->inst.size();
   hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, st, ctl, words, 0u);
   const int workers = plan->num_cu * plan->tiles.workers_per_cu;
-  hipLaunchKernelGGL(batch_kernel, dim3((unsigned)workers), dim3(kBT), 0, st, (const BItem*)plan->d_items,
-                     plan->nitems, (const BInst*)plan->d_inst, ws, ctl, plan->ctx->flags);
+  if (plan->tiles.workers_per_cu == 1)
+    hipLaunchKernelGGL(batch_kernel<1>, dim3((unsigned)workers), dim3(kBT), 0, st, (const BItem*)plan->d_items,
+                       plan->nitems, (const BInst*)plan->d_inst, ws, ctl, plan->ctx->flags);
+  else
+    hipLaunchKernelGGL(batch_kernel<2>, dim3((unsigned)workers), dim3(kBT), 0, st, (const BItem*)plan->d_items,
+                       plan->nitems, (const BInst*)plan->d_inst, ws, ctl, plan->ctx->flags);
   return hipGetLastError() == hipSuccess ? LRE_OK : LRE_E_HIP;
 }
 
@@ -482,7 +501,7 @@ lre_status lre_batch_tune(lre_batch* plan, void* workspace, size_t workspace_byt
   for (int w : {1, 2})
     for (int ct : {1, 2, 4})
       for (int fc : {kBT * 4, kBT * 16})
-        for (int rb : {4, 16})
+        for (int rb : {1, 2, 4})
           for (int il : {0, 1}) {
             const lre_batch_tiles t{w, ct, fc, rb, il};
             if ((s = lre_batch_set_tiles(plan, &t)) != LRE_OK) goto done;

@@ -318,6 +318,38 @@ __device__ __forceinline__ void wht_lanes1(T& x, const int32_t* sg) {
   }
 }
 
+// wht_lanes1 on N independent values, stage by stage, so that the DPP moves of the N
+// chains interleave (no wait states between a stage and the next).
+template <int NL, bool MAD24, int N, typename T>
+__device__ __forceinline__ void wht_lanes_n(T* x, const int32_t* sg) {
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    if constexpr (NL == 1) lane_bfly<kDppQuadXor1, MAD24>(x[j], sg[0]);
+    if constexpr (NL == 2) lane_bfly<kDppQuadXor1, MAD24>(x[j], sg[0]);
+    if constexpr (NL == 3) lane_bfly<kDppHalfMirror, MAD24>(x[j], sg[0]);
+    if constexpr (NL == 4) lane_bfly<kDppMirror, MAD24>(x[j], sg[0]);
+  }
+  if constexpr (NL >= 2) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      if constexpr (NL == 2) lane_bfly<kDppQuadXor2, MAD24>(x[j], sg[1]);
+      if constexpr (NL == 3) lane_bfly<kDppQuadXor1, MAD24>(x[j], sg[1]);
+      if constexpr (NL == 4) lane_bfly<kDppHalfMirror, MAD24>(x[j], sg[1]);
+    }
+  }
+  if constexpr (NL >= 3) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      if constexpr (NL == 3) lane_bfly<kDppQuadXor2, MAD24>(x[j], sg[2]);
+      if constexpr (NL == 4) lane_bfly<kDppQuadXor1, MAD24>(x[j], sg[2]);
+    }
+  }
+  if constexpr (NL >= 4) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) lane_bfly<kDppQuadXor2, MAD24>(x[j], sg[3]);
+  }
+}
+
 // Sum of a 32-bit value over the 2^NL lanes of a row group (result valid in every lane).
 template <int NL>
 __device__ __forceinline__ uint32_t lane_sum(uint32_t x) {
@@ -344,10 +376,15 @@ struct StreamGeom {
 // qubits], the lane letters XOR-swizzled by the register letters.  An emission (one
 // register-letter code for the whole wave, lane letters differing) and the write-out
 // (consecutive a, i.e. consecutive register letters) both spread over the banks.
+// For 4 lane qubits the top letter (bits 6-7) is also folded into the low bits (a
+// bijection), which spreads the 16 lanes of a group and the 4 groups of a wave over
+// more banks (fewer passes per binary64 atomic; modelled on the host).
 template <int Q, int LB>
 __device__ __forceinline__ uint32_t stream_slot_of(uint32_t areg, uint32_t alane) {
   constexpr uint32_t hmask = (1u << (2 * (Q - LB))) - 1;
-  return (areg << (2 * (Q - LB))) | (alane ^ (areg & hmask));
+  uint32_t u = alane ^ (areg & hmask);
+  if constexpr (Q - LB == 4) u = (u & 0xC0u) | ((u ^ ((u >> 6) * 9u)) & 0x3Fu);
+  return (areg << (2 * (Q - LB))) | u;
 }
 
 template <int Q, int LB>
@@ -358,7 +395,7 @@ __device__ __forceinline__ uint32_t stream_slot(uint32_t a) {
 // One block of the counts pass: block index `blk` -> (b_hi, run of `chunks` s_hi tiles).
 // acc / rs_acc: LDS of NACC accumulators and NROWS row totals.  Every thread of the
 // block calls this (it synchronises the block).
-template <int Q, int THREADS, typename Acc, bool PER_BASIS, Out MODE, bool MAD24>
+template <int Q, int THREADS, typename Acc, bool PER_BASIS, Out MODE, bool MAD24, bool PREFETCH = PER_BASIS>
 __device__ __forceinline__ void counts_block(const uint16_t* __restrict__ counts, int n, int chunks,
                                              const double* __restrict__ inv_nb, void* __restrict__ out,
                                              uint32_t* __restrict__ rowpart, uint64_t shots, int64_t blk,
@@ -402,15 +439,10 @@ __device__ __forceinline__ void counts_block(const uint16_t* __restrict__ counts
     if constexpr (LB == 3) {
       // A step is 9 rows (basis digits d0, d1 of qubits 0, 1) at fixed d2 of row-set rs;
       // a group walks steps (rs, 0), (rs, 1), (rs, 2), (rs + GROUPS, 0), ...
-      constexpr bool PREFETCH = PER_BASIS;   // binary64 path: latency-bound without it
       Acc L1[4][2], L2[4][4];
 #pragma unroll
       for (int a = 0; a < 4; ++a) { L1[a][0] = L1[a][1] = Acc(0); L2[a][0] = L2[a][1] = L2[a][2] = L2[a][3] = Acc(0); }
       uint32_t ulane = 0;
-      auto emit = [&](Acc v, uint32_t areg) __attribute__((always_inline)) {
-        wht_lanes1<G::LL, MAD24>(v, sg);
-        atomicAdd(&acc[stream_slot_of<Q, LB>(areg, ulane)], v);
-      };
       auto load9 = [&](uint32_t (&buf)[9][4], double& invr, int rs, int d2) __attribute__((always_inline)) {
         const int rr = rs * G::NSEQ + 9 * d2;
         const uint16_t* __restrict__ p = cchunk + (int64_t)rr * rowlen;
@@ -418,12 +450,20 @@ __device__ __forceinline__ void counts_block(const uint16_t* __restrict__ counts
         for (int r = 0; r < 9; ++r) load_raw<8>(p + (int64_t)r * rowlen, buf[r]);
         if constexpr (PER_BASIS && G::LPC >= 9) invr = inv_nb[row0 + rr + (lam < 9 ? lam : 0)];  // lane r: row r
       };
+      // Four emissions at once: lane butterflies interleaved, then the four LDS adds.
+      auto emit4 = [&](Acc (&v)[4], const uint32_t (&areg)[4]) __attribute__((always_inline)) {
+        wht_lanes_n<G::LL, MAD24, 4>(v, sg);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) atomicAdd(&acc[stream_slot_of<Q, LB>(areg[j], ulane)], v[j]);
+      };
       auto step = [&](const uint32_t (&raw)[9][4], double invr, int rs, int d2) __attribute__((always_inline)) {
         if (d2 == 0) ulane = ulane_of(rs);
         const int rr = rs * G::NSEQ + 9 * d2;
+        const uint32_t a2 = 16u * (uint32_t)(d2 + 1);
         StaticFor<0, 3>::run([&](auto d1c) __attribute__((always_inline)) {
           constexpr int d1 = decltype(d1c)::value;
           Acc L0[4] = {Acc(0), Acc(0), Acc(0), Acc(0)};
+          Acc pend[4];   // the (X/Y/Z, X/Y/Z, X/Y/Z) value of each of the 3 rows, then L0's
           StaticFor<0, 3>::run([&](auto d0c) __attribute__((always_inline)) {
             constexpr int d0 = decltype(d0c)::value;
             constexpr int r = 3 * d1 + d0;
@@ -450,13 +490,9 @@ __device__ __forceinline__ void counts_block(const uint16_t* __restrict__ counts
               L0[mr] += y[2 * mr];
               const Acc w = y[2 * mr + 1];
               const int m1 = mr & 1, m2 = mr >> 1;
-              if (m1 == 0) {
-                L1[d0 + 1][m2] += w;
-              } else if (m2 == 0) {
-                L2[d0 + 1][d1 + 1] += w;
-              } else {
-                emit(w, (uint32_t)((d0 + 1) + 4 * (d1 + 1) + 16 * (d2 + 1)));
-              }
+              if (m1 == 0) L1[d0 + 1][m2] += w;
+              else if (m2 == 0) L2[d0 + 1][d1 + 1] += w;
+              else pend[d0] = w;
             }
           });
           // End of the qubit-0 walk: its identity sums move up (letter I at qubit 0).
@@ -465,25 +501,34 @@ __device__ __forceinline__ void counts_block(const uint16_t* __restrict__ counts
             const int m1 = mr & 1, m2 = mr >> 1;
             if (m1 == 0) L1[0][m2] += L0[mr];
             else if (m2 == 0) L2[0][d1 + 1] += L0[mr];
-            else emit(L0[mr], (uint32_t)(4 * (d1 + 1) + 16 * (d2 + 1)));
+            else pend[3] = L0[mr];
           }
+          const uint32_t ar[4] = {1u + 4u * (d1 + 1) + a2, 2u + 4u * (d1 + 1) + a2, 3u + 4u * (d1 + 1) + a2,
+                                  4u * (d1 + 1) + a2};
+          emit4(pend, ar);
         });
         // End of the qubit-1 walk (letters of qubit 1 now final).
+        {
+          Acc v1[4];
+          const uint32_t ar[4] = {0u + a2, 1u + a2, 2u + a2, 3u + a2};
 #pragma unroll
-        for (int a0 = 0; a0 < 4; ++a0) {
-          L2[a0][0] += L1[a0][0];
-          emit(L1[a0][1], (uint32_t)(a0 + 16 * (d2 + 1)));
-          L1[a0][0] = L1[a0][1] = Acc(0);
+          for (int a0 = 0; a0 < 4; ++a0) {
+            L2[a0][0] += L1[a0][0];
+            v1[a0] = L1[a0][1];
+            L1[a0][0] = L1[a0][1] = Acc(0);
+          }
+          emit4(v1, ar);
         }
         if (d2 == 2) {
           // End of the qubit-2 walk: identity letter at qubit 2.
 #pragma unroll
-          for (int a0 = 0; a0 < 4; ++a0)
+          for (int a1 = 0; a1 < 4; ++a1) {
+            Acc v2[4] = {L2[0][a1], L2[1][a1], L2[2][a1], L2[3][a1]};
+            const uint32_t ar[4] = {0u + 4u * a1, 1u + 4u * a1, 2u + 4u * a1, 3u + 4u * a1};
+            emit4(v2, ar);
 #pragma unroll
-            for (int a1 = 0; a1 < 4; ++a1) {
-              emit(L2[a0][a1], (uint32_t)(a0 + 4 * a1));
-              L2[a0][a1] = Acc(0);
-            }
+            for (int a0 = 0; a0 < 4; ++a0) L2[a0][a1] = Acc(0);
+          }
         }
       };
       if constexpr (PREFETCH) {
@@ -1114,6 +1159,50 @@ __device__ __forceinline__ void rho_high_block(const double2* __restrict__ tmp, 
     const int64_t col = ((int64_t)(r_hi ^ x_hi) << J) | (r_lo ^ x_lo);
     store_complex<OutT>(rho, row * dn + col, re[xo * NHP + r_hi] * scale, im[xo * NHP + r_hi] * scale);
   }
+}
+
+// High transform with H <= 4 high qubits in registers: one element t = (x_hi, r_lo, x_lo)
+// per call (x_lo fastest, so reads of tmp and writes of mu are coalesced); the 2^H
+// values over z_hi are transformed in registers and written to the 2^H rows r_hi.
+template <int H, typename OutT>
+__device__ __forceinline__ void rho_high_reg(const double2* __restrict__ tmp, void* __restrict__ rho, int n, int J,
+                                             int64_t t) {
+  constexpr int NH = 1 << H;
+  const int64_t D = (int64_t)1 << J;
+  const int64_t x_lo = t & (D - 1);
+  const int64_t r_lo = (t >> J) & (D - 1);
+  const int x_hi = (int)(t >> (2 * J));
+  double re[NH], im[NH];
+#pragma unroll
+  for (int z = 0; z < NH; ++z) {
+    int64_t a_hi = 0;
+#pragma unroll
+    for (int p = H - 1; p >= 0; --p) {
+      const int xb = (x_hi >> p) & 1, zb = (z >> p) & 1;
+      a_hi = a_hi * 4 + (xb ? (zb ? 2 : 1) : (zb ? 3 : 0));
+    }
+    const double2 v = tmp[(a_hi * D + r_lo) * D + x_lo];
+    re[z] = v.x;
+    im[z] = v.y;
+    mul_neg_i_pow(__popc((unsigned)(x_hi & z)), re[z], im[z]);
+  }
+  wht_regs<H>(re);
+  wht_regs<H>(im);
+  const double scale = ldexp(1.0, -n);
+  const int64_t dn = (int64_t)1 << n;
+#pragma unroll
+  for (int r_hi = 0; r_hi < NH; ++r_hi) {
+    const int64_t row = ((int64_t)r_hi << J) | r_lo;
+    const int64_t col = ((int64_t)(r_hi ^ x_hi) << J) | (r_lo ^ x_lo);
+    store_complex<OutT>(rho, row * dn + col, re[r_hi] * scale, im[r_hi] * scale);
+  }
+}
+
+template <int H, typename OutT>
+__global__ __launch_bounds__(256) void rho_high_reg_kernel(const double2* __restrict__ tmp, void* __restrict__ rho,
+                                                           int n, int J, int64_t count) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t < count) rho_high_reg<H, OutT>(tmp, rho, n, J, t);
 }
 
 template <int XB, int HMAX, typename OutT>
