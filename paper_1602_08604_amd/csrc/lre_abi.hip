@@ -2,6 +2,7 @@
 // workspace layout and kernel launches.  All arithmetic runs in lre_kernels.hpp.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cstdint>
 #include <cstring>
@@ -22,8 +23,6 @@ constexpr int kMaxQ1 = 7;     // qubits folded by the counts pass
 constexpr int kMaxF = 3;      // qubits folded by a later pass
 constexpr int kMaxFLast = 2;  // qubits folded by the final pass
 constexpr int kRhoJ = 6;      // qubits of the low step-(ii) transform
-constexpr int kRhoXB = 8;     // row entries per block in the high step-(ii) transform
-constexpr int kRhoHMax = LRE_MAX_QUBITS - kRhoJ;
 constexpr int kRhoRegH = 4;   // high step-(ii) qubits transformed in registers (n <= 10)
 
 enum class Ty : int { U32 = 0, F64 = 1 };
@@ -143,18 +142,27 @@ constexpr int fold1_threads() {
 
 // Waves per SIMD the compiler must leave room for: two blocks per CU when two
 // accumulator tiles fit in LDS (32-bit accumulators), else no constraint.
+// Double-buffered row prefetch with one block per CU (256 registers per lane): faster
+// than two blocks per CU without it for 32-bit tiles too (1.04 vs 1.17 ms at n = 12).
+template <int Q, typename Acc>
+constexpr bool fold1_prefetch() {
+  return true;
+}
+
 template <int Q, typename Acc>
 constexpr int fold1_minwaves() {
   constexpr int waves = (fold1_threads<Q>() + 63) / 64;
   constexpr long lds = (long)StreamGeom<Q>::NACC * (long)sizeof(Acc) + 4L * StreamGeom<Q>::NROWS;
-  return (Q == 7 && 2 * lds <= 160L * 1024) ? (2 * waves + 3) / 4 : 1;
+  return (Q == 7 && !fold1_prefetch<Q, Acc>() && 2 * lds <= 160L * 1024) ? (2 * waves + 3) / 4 : 1;
 }
 
 template <int Q, typename Acc, bool PB, Out M, bool MAD24>
 void launch_fold1(const Fold1Args& a) {
   constexpr int TH = fold1_threads<Q>();
   static_assert(TH <= 1024 && (TH % StreamGeom<Q>::LPC) == 0, "counts-pass block shape");
-  hipLaunchKernelGGL((fold_counts_stream_kernel<Q, TH, Acc, PB, M, MAD24, fold1_minwaves<Q, Acc>()>), dim3((unsigned)a.blocks), dim3(TH), 0,
+  hipLaunchKernelGGL((fold_counts_stream_kernel<Q, TH, Acc, PB, M, MAD24, fold1_minwaves<Q, Acc>(),
+                                               fold1_prefetch<Q, Acc>()>),
+                     dim3((unsigned)a.blocks), dim3(TH), 0,
                      a.st, a.counts, a.n, a.chunks, a.inv, a.out, a.rowpart, a.shots);
 }
 
@@ -298,8 +306,7 @@ void launch_rho(const Plan& P, const double* coef, void* rho, char* ws, hipStrea
     return;
   }
   double2* tmp = reinterpret_cast<double2*>(ws + P.off_tmp);
-  hipLaunchKernelGGL((rho_low_kernel<kRhoJ, false, OutT>), dim3((unsigned)ipow4(n - kRhoJ)), dim3(256), 0, st,
-                     coef, (void*)tmp, n);
+  hipLaunchKernelGGL(rho_low6_kernel, dim3((unsigned)ipow4(n - kRhoJ)), dim3(256), 0, st, coef, tmp);
   const int64_t D = (int64_t)1 << kRhoJ;
   if (n - kRhoJ <= kRhoRegH) {
     // few high qubits: one thread per (x_hi, r_lo, x_lo), transform in registers
@@ -313,9 +320,16 @@ void launch_rho(const Plan& P, const double* coef, void* rho, char* ws, hipStrea
     }
     return;
   }
-  const int64_t blocks = ((int64_t)1 << (n - kRhoJ)) * D * (D / kRhoXB);
-  hipLaunchKernelGGL((rho_high_kernel<kRhoXB, kRhoHMax, OutT>), dim3((unsigned)blocks), dim3(256), 0, st,
-                     (const double2*)tmp, rho, n, (int)kRhoJ);
+  // 5..8 high qubits: two register phases with one LDS transpose
+  const int H = n - kRhoJ;
+  const int64_t xb = std::min<int64_t>(D, 4096 >> H);
+  const dim3 grid((unsigned)(((int64_t)1 << H) * D * (D / xb)));
+  switch (H) {
+    case 5: hipLaunchKernelGGL((rho_high2_kernel<5, OutT>), grid, dim3(256), 0, st, (const double2*)tmp, rho, n); break;
+    case 6: hipLaunchKernelGGL((rho_high2_kernel<6, OutT>), grid, dim3(256), 0, st, (const double2*)tmp, rho, n); break;
+    case 7: hipLaunchKernelGGL((rho_high2_kernel<7, OutT>), grid, dim3(256), 0, st, (const double2*)tmp, rho, n); break;
+    default: hipLaunchKernelGGL((rho_high2_kernel<8, OutT>), grid, dim3(256), 0, st, (const double2*)tmp, rho, n); break;
+  }
 }
 
 

@@ -85,7 +85,7 @@ __device__ __forceinline__ void small_rho(const BInst& I, int tid, char* ws, dou
     rho_low_block<Q, true, OutT, kBT>(I.coef, I.rho, I.n, 0, tid, re, im);
   } else {
     for (int64_t a = 0; a < 4; ++a) {
-      rho_low_block<kJ, false, OutT, kBT>(I.coef, ws + I.off_tmp, I.n, a, tid, re, im);
+      rho_low6_block<kBT>(I.coef, reinterpret_cast<double2*>(ws + I.off_tmp), a, tid, re);
       __syncthreads();
     }
     rho_high_range<OutT>(I, 0, (int64_t)2 * 64 * 64, tid, ws);
@@ -148,7 +148,7 @@ __device__ __noinline__ void run_rho(const BInst& I, int64_t x0, int64_t x1, int
         const int xb = (int)(xh >> p) & 1, zb = (z >> p) & 1;
         a_hi = a_hi * 4 + (xb ? (zb ? 2 : 1) : (zb ? 3 : 0));
       }
-      rho_low_block<kJ, false, OutT, kBT>(I.coef, ws + I.off_tmp, I.n, a_hi, tid, re, im);
+      rho_low6_block<kBT>(I.coef, reinterpret_cast<double2*>(ws + I.off_tmp), a_hi, tid, re);
       __syncthreads();
     }
     rho_high_range<OutT>(I, xh * kRhoElemsPerBlock, (xh + 1) * kRhoElemsPerBlock, tid, ws);

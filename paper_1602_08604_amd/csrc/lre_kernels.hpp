@@ -18,19 +18,22 @@
 // Pauli letters.  Qubit positions count from the least significant (position p has
 // weight 3^p in b, 2^p in s, 4^p in the Pauli index), so the lowest qubits fold first.
 //
-// Pass 1 (fold_counts_kernel) streams the uint16 counts once and folds the lowest Q
-// qubits: a tile is 3^Q rows x 2^Q consecutive outcomes; each lane owns 8 outcomes of
-// 9 rows, does the butterflies in registers and across the LPC lanes of the tile
-// row, folds the 2 lowest qubits in registers and adds the result into a 4^Q LDS
-// accumulator.  Later passes (fold_partial_kernel) fold up to 3 more qubits per pass,
-// one thread per column of the fastest-varying a_lo index, entirely in registers.
+// Pass 1 (counts_block / fold_counts_stream_kernel) streams the uint16 counts once and
+// folds the lowest Q <= 7 qubits: a tile is 3^Q rows x 2^Q consecutive outcomes; a lane
+// owns 8 outcomes of a row, a group of 16 lanes walks 27 rows, folds the 3 register
+// qubits with an accumulator cascade, applies the lane butterflies to the values that
+// leave the cascade and adds them into a 4^Q LDS accumulator.  Later passes
+// (fold_partial_col / fold_partial_kernel) fold up to 3 more qubits per pass, one
+// thread per column of the fastest-varying a_lo index, entirely in registers.
 //
 // Step (ii) (Sec. II eq. 4): with x = r XOR c, the entry mu[r][r^x] is a Walsh-Hadamard
 // transform over z in {0,1}^n of e_{a(x,z)} (-i)^{|x&z|}, where per qubit the pair
 // (x_k, z_k) = (0,0),(1,0),(1,1),(0,1) is the letter I, X, Y, Z (the paper's grouping of
-// the Omega_i by nonzero pattern, Sec. IV).  rho_low_kernel transforms the low J
-// qubits of each 4^J block of coefficients; rho_high_kernel the remaining high qubits
-// and writes the row-major matrix.
+// the Omega_i by nonzero pattern, Sec. IV).  n <= 6: rho_low_kernel does all of it in
+// LDS.  n > 6: rho_low6_kernel transforms the low 6 qubits of each 4^6 coefficient
+// block (registers + lane quads), then rho_high_reg_kernel (up to 4 high qubits, in
+// registers) or rho_high2_kernel (5 to 8, two register phases and one LDS transpose)
+// the remaining high qubits, writing the row-major matrix.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -625,14 +628,15 @@ __device__ __forceinline__ void counts_block(const uint16_t* __restrict__ counts
   for (int i = tid; i < G::NROWS; i += THREADS) rp[i] = rs_acc[i];
 }
 
-template <int Q, int THREADS, typename Acc, bool PER_BASIS, Out MODE, bool MAD24, int MINWAVES = 1>
+template <int Q, int THREADS, typename Acc, bool PER_BASIS, Out MODE, bool MAD24, int MINWAVES = 1,
+          bool PREFETCH = PER_BASIS>
 __global__ __launch_bounds__(THREADS, MINWAVES) void fold_counts_stream_kernel(
     const uint16_t* __restrict__ counts, int n, int chunks, const double* __restrict__ inv_nb,
     void* __restrict__ out, uint32_t* __restrict__ rowpart, uint64_t shots) {
   __shared__ Acc acc[StreamGeom<Q>::NACC];
   __shared__ uint32_t rs_acc[StreamGeom<Q>::NROWS];
-  counts_block<Q, THREADS, Acc, PER_BASIS, MODE, MAD24>(counts, n, chunks, inv_nb, out, rowpart, shots,
-                                                       blockIdx.x, threadIdx.x, acc, rs_acc);
+  counts_block<Q, THREADS, Acc, PER_BASIS, MODE, MAD24, PREFETCH>(counts, n, chunks, inv_nb, out, rowpart, shots,
+                                                                 blockIdx.x, threadIdx.x, acc, rs_acc);
 }
 
 // ---------------------------------------------------------------------------------
@@ -1105,62 +1109,6 @@ __global__ __launch_bounds__(256) void rho_low_kernel(const double* __restrict__
   rho_low_block<J, FINAL, OutT, 256>(coef, out, n, blockIdx.x, threadIdx.x, re, im);
 }
 
-// Transform the high H = n - J qubits and write mu row-major.  Block -> (x_hi, r_lo,
-// block of XB consecutive x_lo); the XB entries of a row are adjacent in memory.
-// re, im: LDS planes of at least XB * (2^(n-J) + 1) doubles ([xo][z], padded rows).
-template <int XB, typename OutT, int THREADS>
-__device__ __forceinline__ void rho_high_block(const double2* __restrict__ tmp, void* __restrict__ rho,
-                                               int n, int J, int64_t bid, int tid,
-                                               double* __restrict__ re, double* __restrict__ im) {
-  const int H = n - J;
-  const int NH = 1 << H;
-  const int NHP = NH + 1;  // padded row stride
-  const int D = 1 << J;
-  const int xblk = (int)(bid % (D / XB));
-  bid /= (D / XB);
-  const int r_lo = (int)(bid % D);
-  const int64_t x_hi = bid / D;
-  const int tile = NH * XB;
-  for (int t = tid; t < tile; t += THREADS) {
-    const int z = t / XB, xo = t % XB;
-    const int x_lo = xblk * XB + xo;
-    int64_t a_hi = 0;
-    for (int p = H - 1; p >= 0; --p) {
-      const int xb = (x_hi >> p) & 1, zb = (z >> p) & 1;
-      a_hi = a_hi * 4 + (xb ? (zb ? 2 : 1) : (zb ? 3 : 0));
-    }
-    const double2 v = tmp[(a_hi * D + r_lo) * D + x_lo];
-    double vr = v.x, vi = v.y;
-    mul_neg_i_pow(__popc((unsigned)(x_hi & z)), vr, vi);
-    re[xo * NHP + z] = vr;
-    im[xo * NHP + z] = vi;
-  }
-  __syncthreads();
-  for (int bit = 0; bit < H; ++bit) {
-    for (int t = tid; t < tile / 2; t += THREADS) {
-      const int xo = t / (NH / 2), k = t % (NH / 2);
-      const int lo = ((k >> bit) << (bit + 1)) | (k & ((1 << bit) - 1));
-      const int hi = lo | (1 << bit);
-      const double a = re[xo * NHP + lo], b = re[xo * NHP + hi];
-      re[xo * NHP + lo] = a + b;
-      re[xo * NHP + hi] = a - b;
-      const double c = im[xo * NHP + lo], f = im[xo * NHP + hi];
-      im[xo * NHP + lo] = c + f;
-      im[xo * NHP + hi] = c - f;
-    }
-    __syncthreads();
-  }
-  const double scale = ldexp(1.0, -n);
-  const int64_t dn = (int64_t)1 << n;
-  for (int t = tid; t < tile; t += THREADS) {
-    const int r_hi = t / XB, xo = t % XB;
-    const int x_lo = xblk * XB + xo;
-    const int64_t row = ((int64_t)r_hi << J) | r_lo;
-    const int64_t col = ((int64_t)(r_hi ^ x_hi) << J) | (r_lo ^ x_lo);
-    store_complex<OutT>(rho, row * dn + col, re[xo * NHP + r_hi] * scale, im[xo * NHP + r_hi] * scale);
-  }
-}
-
 // High transform with H <= 4 high qubits in registers: one element t = (x_hi, r_lo, x_lo)
 // per call (x_lo fastest, so reads of tmp and writes of mu are coalesced); the 2^H
 // values over z_hi are transformed in registers and written to the 2^H rows r_hi.
@@ -1205,11 +1153,132 @@ __global__ __launch_bounds__(256) void rho_high_reg_kernel(const double2* __rest
   if (t < count) rho_high_reg<H, OutT>(tmp, rho, n, J, t);
 }
 
-template <int XB, int HMAX, typename OutT>
-__global__ __launch_bounds__(256) void rho_high_kernel(const double2* __restrict__ tmp,
-                                                       void* __restrict__ rho, int n, int J) {
-  __shared__ double re[XB * ((1 << HMAX) + 1)], im[XB * ((1 << HMAX) + 1)];
-  rho_high_block<XB, OutT, 256>(tmp, rho, n, J, blockIdx.x, threadIdx.x, re, im);
+// Bit p of v moved to bit 2p (6 bits).
+__device__ __forceinline__ uint32_t spread6(uint32_t v) {
+  uint32_t r = 0;
+#pragma unroll
+  for (int p = 0; p < 6; ++p) r |= ((v >> p) & 1u) << (2 * p);
+  return r;
+}
+
+// Low transform of one block of 4^6 coefficients (block a_hi).
+// The block is staged in LDS with coalesced loads; thread (x, zl) = (t / 4, t % 4)
+// gathers its 16 values z = zl + 4k (letter digit x_p ^ 3 z_p: I, X, Y, Z for (x, z)
+// bits (0,0), (1,0), (1,1), (0,1)), transforms z bits 2-5 in registers and bits 0-1
+// across its lane quad (DPP, exact butterflies), and writes tmp[a_hi][r][x].
+// blk: LDS of 4096 doubles.  Every thread of the block calls this (it synchronises);
+// threads 0..255 do the transform, the caller synchronises before reusing blk.
+template <int THREADS>
+__device__ __forceinline__ void rho_low6_block(const double* __restrict__ coef, double2* __restrict__ tmp,
+                                               int64_t a_hi, int t, double* __restrict__ blk) {
+  static_assert(THREADS >= 256, "one thread per (x, z quad)");
+  const double* __restrict__ e = coef + a_hi * 4096;
+  for (int i = t; i < 4096; i += THREADS) blk[i] = e[i];
+  __syncthreads();
+  if (t < 256) {
+    const uint32_t x = (uint32_t)t >> 2, zl = (uint32_t)t & 3u;
+    const uint32_t sx = spread6(x);
+    double re[16], im[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const uint32_t z = zl + 4u * (uint32_t)k;
+      const uint32_t sz = spread6(z);
+      re[k] = blk[sx ^ sz ^ (sz << 1)];
+      im[k] = 0.0;
+      mul_neg_i_pow(__popc(x & z), re[k], im[k]);
+    }
+    wht_regs<4>(re);
+    wht_regs<4>(im);
+    int32_t sg[2] = {(t & 1) ? -1 : 1, (t & 2) ? -1 : 1};
+    asm volatile("" : "+v"(sg[0]), "+v"(sg[1]));
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      lane_bfly<kDppQuadXor1, false>(re[k], sg[0]);
+      lane_bfly<kDppQuadXor1, false>(im[k], sg[0]);
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      lane_bfly<kDppQuadXor2, false>(re[k], sg[1]);
+      lane_bfly<kDppQuadXor2, false>(im[k], sg[1]);
+    }
+    double2* __restrict__ o = tmp + a_hi * 4096;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) o[(zl + 4u * (uint32_t)k) * 64u + x] = make_double2(re[k], im[k]);
+  }
+}
+
+static __global__ __launch_bounds__(256) void rho_low6_kernel(const double* __restrict__ coef, double2* __restrict__ tmp) {
+  __shared__ double blk[4096];
+  rho_low6_block<256>(coef, tmp, blockIdx.x, threadIdx.x, blk);
+}
+
+// High transform for H = n - 6 in [5, 8] high qubits, 256 threads.  Block -> (x_hi, r_lo,
+// block of XB consecutive x_lo).  z = zA + 16 zB: phase A transforms zA (4 bits) in
+// registers per (x_lo, zB) and stores to LDS; phase B transforms zB (H - 4 bits) in
+// registers per (x_lo, zA) and writes rows r_hi = zA' + 16 zB' of mu.
+template <int H, typename OutT>
+__global__ __launch_bounds__(256) void rho_high2_kernel(const double2* __restrict__ tmp, void* __restrict__ rho,
+                                                        int n) {
+  constexpr int J = 6, D = 64, NH = 1 << H, HB = H - 4, NB = 1 << HB;
+  constexpr int XB = (4096 / NH) < D ? (4096 / NH) : D;
+  constexpr int SP = XB + 1;  // padded LDS row (one z) stride
+  __shared__ double sre[NH * SP], sim[NH * SP];
+  int64_t bid = blockIdx.x;
+  const int xblk = (int)(bid % (D / XB));
+  bid /= (D / XB);
+  const int r_lo = (int)(bid % D);
+  const int x_hi = (int)(bid / D);
+  const int t = threadIdx.x;
+  // phase A: items (xo, zB), xo fastest
+  for (int it = t; it < XB * NB; it += 256) {
+    const int xo = it % XB, zB = it / XB;
+    const int x_lo = xblk * XB + xo;
+    double re[16], im[16];
+#pragma unroll
+    for (int zA = 0; zA < 16; ++zA) {
+      const int z = zA + 16 * zB;
+      int64_t a_hi = 0;
+#pragma unroll
+      for (int p = H - 1; p >= 0; --p) {
+        const int xb = (x_hi >> p) & 1, zb = (z >> p) & 1;
+        a_hi = a_hi * 4 + (xb ? (zb ? 2 : 1) : (zb ? 3 : 0));
+      }
+      const double2 v = tmp[(a_hi * D + r_lo) * D + x_lo];
+      re[zA] = v.x;
+      im[zA] = v.y;
+      mul_neg_i_pow(__popc((unsigned)(x_hi & z)), re[zA], im[zA]);
+    }
+    wht_regs<4>(re);
+    wht_regs<4>(im);
+#pragma unroll
+    for (int zA = 0; zA < 16; ++zA) {
+      sre[(zA + 16 * zB) * SP + xo] = re[zA];
+      sim[(zA + 16 * zB) * SP + xo] = im[zA];
+    }
+  }
+  __syncthreads();
+  const double scale = ldexp(1.0, -n);
+  const int64_t dn = (int64_t)1 << n;
+  // phase B: items (xo, zA), xo fastest
+  for (int it = t; it < XB * 16; it += 256) {
+    const int xo = it % XB, zA = it / XB;
+    const int x_lo = xblk * XB + xo;
+    double re[NB], im[NB];
+#pragma unroll
+    for (int zB = 0; zB < NB; ++zB) {
+      re[zB] = sre[(zA + 16 * zB) * SP + xo];
+      im[zB] = sim[(zA + 16 * zB) * SP + xo];
+    }
+    wht_regs<HB>(re);
+    wht_regs<HB>(im);
+#pragma unroll
+    for (int zB = 0; zB < NB; ++zB) {
+      const int r_hi = zA + 16 * zB;
+      const int64_t row = ((int64_t)r_hi << J) | r_lo;
+      const int64_t col = ((int64_t)(r_hi ^ x_hi) << J) | (r_lo ^ x_lo);
+      store_complex<OutT>(rho, row * dn + col, re[zB] * scale, im[zB] * scale);
+    }
+  }
 }
 
 }  // namespace lre
