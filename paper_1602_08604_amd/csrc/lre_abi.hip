@@ -267,11 +267,17 @@ void launch_foldk(const FoldKArgs& a) {
 
 template <int F, typename Tin, typename Acc>
 bool foldk_m(Out m, const FoldKArgs& a) {
-  switch (m) {
-    case Out::Partial: launch_foldk<F, Tin, Acc, Out::Partial>(a); return true;
-    case Out::CoefUniform: launch_foldk<F, Tin, Acc, Out::CoefUniform>(a); return true;
-    case Out::CoefPerBasis: launch_foldk<F, Tin, Acc, Out::CoefPerBasis>(a); return true;
-    case Out::PauliT: launch_foldk<F, Tin, Acc, Out::PauliT>(a); return true;
+  if constexpr (F > kMaxFLast) {  // only the final pass writes coefficients
+    if (m != Out::Partial) return false;
+    launch_foldk<F, Tin, Acc, Out::Partial>(a);
+    return true;
+  } else {
+    switch (m) {
+      case Out::Partial: launch_foldk<F, Tin, Acc, Out::Partial>(a); return true;
+      case Out::CoefUniform: launch_foldk<F, Tin, Acc, Out::CoefUniform>(a); return true;
+      case Out::CoefPerBasis: launch_foldk<F, Tin, Acc, Out::CoefPerBasis>(a); return true;
+      case Out::PauliT: launch_foldk<F, Tin, Acc, Out::PauliT>(a); return true;
+    }
   }
   return false;
 }

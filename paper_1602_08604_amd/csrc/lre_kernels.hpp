@@ -882,41 +882,87 @@ __device__ __forceinline__ void fold_partial_col(const Tin* __restrict__ in, voi
   const Tin* __restrict__ p0 = in + b_hi * ipow3(F) * rowstride + (s_hi << F) * L + a_l;
 
   constexpr int NA = (int)ipow4(F);
-  Acc acc[NA];
-  StaticFor<0, NA>::run([&](auto ac) __attribute__((always_inline)) { acc[decltype(ac)::value] = Acc(0); });
-  StaticFor<0, (int)ipow3(F)>::run([&](auto bc) __attribute__((always_inline)) {
-    constexpr int beta = decltype(bc)::value;
-    Acc x[1 << F];
-#pragma unroll
-    for (int sg = 0; sg < (1 << F); ++sg) x[sg] = in_to_acc<Tin, Acc>(p0[beta * rowstride + sg * L]);
-    wht_regs<F>(x);
-    StaticFor<0, (1 << F)>::run([&](auto mc) __attribute__((always_inline)) {
-      constexpr int m = decltype(mc)::value;
-      constexpr int a = fold_index(beta, m, F);
-      acc[a] += x[m];
-    });
-  });
-
-  if constexpr (MODE == Out::Partial) {
-    Acc* o = static_cast<Acc*>(out) + bs * (NA * L) + a_l;
-    StaticFor<0, NA>::run([&](auto ac) __attribute__((always_inline)) {
-      constexpr int a = decltype(ac)::value;
-      o[a * L] = acc[a];
-    });
-  } else {
-    const int wl = pauli_weight((uint64_t)a_l);
-    StaticFor<0, NA>::run([&](auto ac) __attribute__((always_inline)) {
-      constexpr int a = decltype(ac)::value;
+  // Final value of folded letter code a (compile-time) for this column.
+  const int wl = MODE == Out::Partial ? 0 : pauli_weight((uint64_t)a_l);
+  auto put = [&](auto ac, Acc v) __attribute__((always_inline)) {
+    constexpr int a = decltype(ac)::value;
+    if constexpr (MODE == Out::Partial) {
+      static_cast<Acc*>(out)[bs * (NA * L) + a * L + a_l] = v;
+    } else {
       const int64_t i = a * L + a_l;
       const int w = wl + __builtin_popcount((a | (a >> 1)) & 0x55555555);
       if constexpr (MODE == Out::CoefUniform)
-        static_cast<double*>(out)[i] = acc_to_double(acc[a]) / (pow3d(n - w) * (double)shots);
+        static_cast<double*>(out)[i] = acc_to_double(v) / (pow3d(n - w) * (double)shots);
       else if constexpr (MODE == Out::CoefPerBasis)
-        static_cast<double*>(out)[i] = acc_to_double(acc[a]) / pow3d(n - w);
+        static_cast<double*>(out)[i] = acc_to_double(v) / pow3d(n - w);
       else
-        static_cast<int64_t*>(out)[i] = acc_to_i64(acc[a]);
+        static_cast<int64_t*>(out)[i] = acc_to_i64(v);
+    }
+  };
+  auto load_row = [&](int beta, Acc* x) __attribute__((always_inline)) {
+#pragma unroll
+    for (int sg = 0; sg < (1 << F); ++sg) x[sg] = in_to_acc<Tin, Acc>(p0[beta * rowstride + sg * L]);
+    wht_regs<F>(x);
+  };
+  using I0 = std::integral_constant<int, 0>;
+
+  if constexpr (F == 3) {
+    // Accumulator cascade over the basis digits (d0 innermost): level k holds the
+    // identity-letter sums of position k; a letter code is stored as soon as it is final.
+    Acc L1[4][2], L2[4][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) { L1[q][0] = L1[q][1] = Acc(0); L2[q][0] = L2[q][1] = L2[q][2] = L2[q][3] = Acc(0); }
+    StaticFor<0, 3>::run([&](auto d2c) __attribute__((always_inline)) {
+      constexpr int d2 = decltype(d2c)::value;
+      StaticFor<0, 3>::run([&](auto d1c) __attribute__((always_inline)) {
+        constexpr int d1 = decltype(d1c)::value;
+        Acc L0[4] = {Acc(0), Acc(0), Acc(0), Acc(0)};
+        StaticFor<0, 3>::run([&](auto d0c) __attribute__((always_inline)) {
+          constexpr int d0 = decltype(d0c)::value;
+          Acc y[8];
+          load_row(d0 + 3 * d1 + 9 * d2, y);
+          StaticFor<0, 4>::run([&](auto mrc) __attribute__((always_inline)) {
+            constexpr int mr = decltype(mrc)::value, m1 = mr & 1, m2 = mr >> 1;
+            L0[mr] += y[2 * mr];
+            if constexpr (m1 == 0) L1[d0 + 1][m2] += y[2 * mr + 1];
+            else if constexpr (m2 == 0) L2[d0 + 1][d1 + 1] += y[2 * mr + 1];
+            else put(std::integral_constant<int, (d0 + 1) + 4 * (d1 + 1) + 16 * (d2 + 1)>{}, y[2 * mr + 1]);
+          });
+        });
+        StaticFor<0, 4>::run([&](auto mrc) __attribute__((always_inline)) {
+          constexpr int mr = decltype(mrc)::value, m1 = mr & 1, m2 = mr >> 1;
+          if constexpr (m1 == 0) L1[0][m2] += L0[mr];
+          else if constexpr (m2 == 0) L2[0][d1 + 1] += L0[mr];
+          else put(std::integral_constant<int, 4 * (d1 + 1) + 16 * (d2 + 1)>{}, L0[mr]);
+        });
+      });
+      StaticFor<0, 4>::run([&](auto a0c) __attribute__((always_inline)) {
+        constexpr int a0 = decltype(a0c)::value;
+        L2[a0][0] += L1[a0][0];
+        put(std::integral_constant<int, a0 + 16 * (d2 + 1)>{}, L1[a0][1]);
+        L1[a0][0] = L1[a0][1] = Acc(0);
+      });
     });
+    StaticFor<0, 16>::run([&](auto ac) __attribute__((always_inline)) {
+      constexpr int a = decltype(ac)::value;
+      put(ac, L2[a & 3][a >> 2]);
+    });
+  } else {
+    Acc acc[NA];
+    StaticFor<0, NA>::run([&](auto ac) __attribute__((always_inline)) { acc[decltype(ac)::value] = Acc(0); });
+    StaticFor<0, (int)ipow3(F)>::run([&](auto bc) __attribute__((always_inline)) {
+      constexpr int beta = decltype(bc)::value;
+      Acc x[1 << F];
+      load_row(beta, x);
+      StaticFor<0, (1 << F)>::run([&](auto mc) __attribute__((always_inline)) {
+        constexpr int m = decltype(mc)::value;
+        constexpr int a = fold_index(beta, m, F);
+        acc[a] += x[m];
+      });
+    });
+    StaticFor<0, NA>::run([&](auto ac) __attribute__((always_inline)) { put(ac, acc[decltype(ac)::value]); });
   }
+  (void)sizeof(I0);
 }
 
 template <int F, typename Tin, typename Acc, Out MODE>
