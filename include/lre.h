@@ -165,7 +165,7 @@ typedef struct {
 typedef struct {
   int workers_per_cu;   /* persistent workgroups per compute unit: 1 or 2 */
   int counts_tiles;     /* counts-pass tiles (3^7 rows x 128 outcomes) per item, >= 1 */
-  int fold_cols;        /* later-pass columns per item, multiple of 432 */
+  int fold_cols;        /* later-pass columns per item, multiple of 512 */
   int rho_blocks;       /* step-(ii) work per item, >= 1: high-qubit row patterns x_hi
                            (2^(n-6) per instance of n > 7 qubits) */
   int interleave;       /* 0: stage by stage, largest instances first;

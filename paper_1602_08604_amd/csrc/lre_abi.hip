@@ -132,8 +132,9 @@ struct Fold1Args {
 };
 
 // Counts-pass block: one row group per tile row-set, i.e. NRS * LPC threads (3^Q rows
-// of 2^Q outcomes), split in three for Q = 7 (81 row-sets of 16 lanes -> 432 threads,
-// each group walks three row-sets).
+// of 2^Q outcomes); for Q = 7 (81 row-sets of 16 lanes) 432 threads, 27 groups of three
+// row-sets each.  (512 threads with uneven step ranges is slower: the groups of a wave
+// then flush their row-set sums at different steps and the wave runs both paths.)
 template <int Q>
 constexpr int fold1_threads() {
   constexpr int t = StreamGeom<Q>::NRS * StreamGeom<Q>::LPC;

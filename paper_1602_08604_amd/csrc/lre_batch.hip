@@ -33,7 +33,7 @@ using lre_detail::DeviceGuard;
 
 namespace {
 
-constexpr int kBT = 432;          // threads of a persistent workgroup (27 row groups of 16 lanes)
+constexpr int kBT = 512;          // threads of a persistent workgroup (32 row groups of 16 lanes)
 constexpr int kQ = 7;             // counts-pass tile qubits (n >= 7)
 constexpr int kJ = 6;             // low step-(ii) qubits (n > 6)
 constexpr uint32_t kWaitLimit = 1u << 24;  // sleeps of ~64 clocks before a wait gives up

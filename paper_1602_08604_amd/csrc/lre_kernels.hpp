@@ -459,8 +459,11 @@ __device__ __forceinline__ void counts_block(const uint16_t* __restrict__ counts
 #pragma unroll
         for (int j = 0; j < 4; ++j) atomicAdd(&acc[stream_slot_of<Q, LB>(areg[j], ulane)], v[j]);
       };
-      auto step = [&](const uint32_t (&raw)[9][4], double invr, int rs, int d2) __attribute__((always_inline)) {
-        if (d2 == 0) ulane = ulane_of(rs);
+      // first: the group's first step (its row-set's letters are not yet set up);
+      // last: the group's last step (flush the qubit-2 identity sums even mid row-set).
+      auto step = [&](const uint32_t (&raw)[9][4], double invr, int rs, int d2, bool first,
+                      bool last) __attribute__((always_inline)) {
+        if (first || d2 == 0) ulane = ulane_of(rs);
         const int rr = rs * G::NSEQ + 9 * d2;
         const uint32_t a2 = 16u * (uint32_t)(d2 + 1);
         StaticFor<0, 3>::run([&](auto d1c) __attribute__((always_inline)) {
@@ -522,8 +525,8 @@ __device__ __forceinline__ void counts_block(const uint16_t* __restrict__ counts
           }
           emit4(v1, ar);
         }
-        if (d2 == 2) {
-          // End of the qubit-2 walk: identity letter at qubit 2.
+        if (d2 == 2 || last) {
+          // End of the qubit-2 walk (or of this group's part of it): identity letter at qubit 2.
 #pragma unroll
           for (int a1 = 0; a1 < 4; ++a1) {
             Acc v2[4] = {L2[0][a1], L2[1][a1], L2[2][a1], L2[3][a1]};
@@ -534,42 +537,43 @@ __device__ __forceinline__ void counts_block(const uint16_t* __restrict__ counts
           }
         }
       };
+      // Steps are numbered s = 3 rs + d2 (243 per tile for Q = 7); group g takes the
+      // contiguous range [s0, s1).  A range may start or end inside a row-set: the
+      // qubit-2 identity sums are then flushed as partial sums, which the LDS adds.
+      constexpr int TOTAL = G::NRS * 3;
+      const int s0 = (int)(((int64_t)grp * TOTAL) / GROUPS);
+      const int s1 = (int)(((int64_t)(grp + 1) * TOTAL) / GROUPS);
       if constexpr (PREFETCH) {
         // Double-buffered: the next step's rows are in flight while this one is folded.
-        uint32_t bufA[9][4], bufB[9][4];
-        double invA = 0.0, invB = 0.0;
         // The prefetch is unconditional (past the last step it re-reads the current rows)
         // so that the wait for the current buffer never has to cover it.
-        int rs = grp, d2 = 0;
-        if (rs < G::NRS) {
-          load9(bufA, invA, rs, 0);
+        uint32_t bufA[9][4], bufB[9][4];
+        double invA = 0.0, invB = 0.0;
+        if (s0 < s1) {
+          int s = s0;
+          load9(bufA, invA, s / 3, s % 3);
           for (;;) {
-            int rs1 = d2 == 2 ? rs + GROUPS : rs, d21 = d2 == 2 ? 0 : d2 + 1;
-            bool more = rs1 < G::NRS;
-            load9(bufB, invB, more ? rs1 : rs, more ? d21 : d2);
-            step(bufA, invA, rs, d2);
+            int sn = s + 1;
+            bool more = sn < s1;
+            load9(bufB, invB, (more ? sn : s) / 3, (more ? sn : s) % 3);
+            step(bufA, invA, s / 3, s % 3, s == s0, !more);
             if (!more) break;
-            rs = rs1;
-            d2 = d21;
-            rs1 = d2 == 2 ? rs + GROUPS : rs;
-            d21 = d2 == 2 ? 0 : d2 + 1;
-            more = rs1 < G::NRS;
-            load9(bufA, invA, more ? rs1 : rs, more ? d21 : d2);
-            step(bufB, invB, rs, d2);
+            s = sn;
+            sn = s + 1;
+            more = sn < s1;
+            load9(bufA, invA, (more ? sn : s) / 3, (more ? sn : s) % 3);
+            step(bufB, invB, s / 3, s % 3, false, !more);
             if (!more) break;
-            rs = rs1;
-            d2 = d21;
+            s = sn;
           }
         }
       } else {
-        for (int rs = grp; rs < G::NRS; rs += GROUPS) {
 #pragma unroll 1
-          for (int d2 = 0; d2 < 3; ++d2) {
-            uint32_t raw[9][4];
-            double invr = 0.0;
-            load9(raw, invr, rs, d2);
-            step(raw, invr, rs, d2);
-          }
+        for (int s = s0; s < s1; ++s) {
+          uint32_t raw[9][4];
+          double invr = 0.0;
+          load9(raw, invr, s / 3, s % 3);
+          step(raw, invr, s / 3, s % 3, s == s0, s + 1 == s1);
         }
       }
     } else {
