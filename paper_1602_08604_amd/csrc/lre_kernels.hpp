@@ -446,11 +446,15 @@ __device__ __forceinline__ void counts_block(const uint16_t* __restrict__ counts
 #pragma unroll
       for (int a = 0; a < 4; ++a) { L1[a][0] = L1[a][1] = Acc(0); L2[a][0] = L2[a][1] = L2[a][2] = L2[a][3] = Acc(0); }
       uint32_t ulane = 0;
-      auto load9 = [&](uint32_t (&buf)[9][4], double& invr, int rs, int d2) __attribute__((always_inline)) {
-        const int rr = rs * G::NSEQ + 9 * d2;
+      // dummy: a prefetch past the group's last step reads the tile's first row segment
+      // nine times (cached) instead of fresh rows.
+      auto load9 = [&](uint32_t (&buf)[9][4], double& invr, int rs, int d2, bool dummy = false)
+                       __attribute__((always_inline)) {
+        const int rr = dummy ? 0 : rs * G::NSEQ + 9 * d2;
         const uint16_t* __restrict__ p = cchunk + (int64_t)rr * rowlen;
+        const int64_t stride = dummy ? 0 : rowlen;
 #pragma unroll
-        for (int r = 0; r < 9; ++r) load_raw<8>(p + (int64_t)r * rowlen, buf[r]);
+        for (int r = 0; r < 9; ++r) load_raw<8>(p + (int64_t)r * stride, buf[r]);
         if constexpr (PER_BASIS && G::LPC >= 9) invr = inv_nb[row0 + rr + (lam < 9 ? lam : 0)];  // lane r: row r
       };
       // Four emissions at once: lane butterflies interleaved, then the four LDS adds.
@@ -545,8 +549,8 @@ __device__ __forceinline__ void counts_block(const uint16_t* __restrict__ counts
       const int s1 = (int)(((int64_t)(grp + 1) * TOTAL) / GROUPS);
       if constexpr (PREFETCH) {
         // Double-buffered: the next step's rows are in flight while this one is folded.
-        // The prefetch is unconditional (past the last step it re-reads the current rows)
-        // so that the wait for the current buffer never has to cover it.
+        // The prefetch is unconditional (past the last step it is a cached dummy read) so
+        // that the wait for the current buffer never has to cover it.
         uint32_t bufA[9][4], bufB[9][4];
         double invA = 0.0, invB = 0.0;
         if (s0 < s1) {
@@ -555,13 +559,13 @@ __device__ __forceinline__ void counts_block(const uint16_t* __restrict__ counts
           for (;;) {
             int sn = s + 1;
             bool more = sn < s1;
-            load9(bufB, invB, (more ? sn : s) / 3, (more ? sn : s) % 3);
+            load9(bufB, invB, sn / 3, sn % 3, !more);
             step(bufA, invA, s / 3, s % 3, s == s0, !more);
             if (!more) break;
             s = sn;
             sn = s + 1;
             more = sn < s1;
-            load9(bufA, invA, (more ? sn : s) / 3, (more ? sn : s) % 3);
+            load9(bufA, invA, sn / 3, sn % 3, !more);
             step(bufB, invB, s / 3, s % 3, false, !more);
             if (!more) break;
             s = sn;
