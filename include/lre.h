@@ -140,8 +140,8 @@ lre_status lre_signed_sums(lre_ctx* ctx, int n, const uint16_t* counts, const in
  * kernels' arithmetic, bit-identical coefficients and rho.
  *
  * lre_batch_plan builds a work list (an instance of n <= 7 qubits is one item; a larger
- * one is split into its counts-pass tiles, row check, later pass and step-(ii) blocks,
- * in dependency order) and uploads it.  lre_batch_run enqueues two kernels: a fill kernel that clears the
+ * one is split into its counts-pass row groups, later pass and step-(ii) blocks, in
+ * dependency order) and uploads it.  lre_batch_run enqueues two kernels: a fill kernel that clears the
  * item and dependency counters in the workspace, then one persistent kernel whose
  * workgroups take items from the list in order; an item that needs the results of
  * earlier items waits for their counters (a bounded wait: on expiry the item is
@@ -164,8 +164,8 @@ typedef struct {
 /* Work-item shape of a plan (what lre_batch_tune chooses between). */
 typedef struct {
   int workers_per_cu;   /* persistent workgroups per compute unit: 1 or 2 */
-  int counts_tiles;     /* counts-pass tiles (3^7 rows x 128 outcomes) per item, >= 1 */
-  int fold_cols;        /* later-pass columns per item, multiple of 512 */
+  int counts_tiles;     /* counts-pass row groups (3^7 rows, all their outcomes) per item, >= 1 */
+  int fold_cols;        /* later-pass columns per item, multiple of 432 */
   int rho_blocks;       /* step-(ii) work per item, >= 1: high-qubit row patterns x_hi
                            (2^(n-6) per instance of n > 7 qubits) */
   int interleave;       /* 0: stage by stage, largest instances first;

@@ -33,12 +33,12 @@ using lre_detail::DeviceGuard;
 
 namespace {
 
-constexpr int kBT = 512;          // threads of a persistent workgroup (32 row groups of 16 lanes)
+constexpr int kBT = 432;          // threads of a persistent workgroup (27 row groups of 16 lanes)
 constexpr int kQ = 7;             // counts-pass tile qubits (n >= 7)
 constexpr int kJ = 6;             // low step-(ii) qubits (n > 6)
 constexpr uint32_t kWaitLimit = 1u << 24;  // sleeps of ~64 clocks before a wait gives up
 
-enum Kind : uint8_t { K_SMALL = 0, K_COUNTS = 1, K_CHECK = 2, K_FOLD = 3, K_RHO = 4 };
+enum Kind : uint8_t { K_SMALL = 0, K_COUNTS = 1, K_FOLD = 3, K_RHO = 4 };
 // variant bits
 enum : uint8_t { V_MAD24 = 16, V_FP32 = 32, V_RHO = 64 };
 
@@ -57,9 +57,37 @@ struct BInst {
   double* coef;
   void* rho;
   uint64_t shots;
-  int64_t off_part, off_rowpart, off_tmp;  // workspace offsets
+  int64_t off_part, off_tmp;  // workspace offsets
   int32_t n, q1;
 };
+
+// Pointers read from the instance table are retyped into the global address space
+// (the compiler cannot infer it for pointers loaded from memory and would otherwise use
+// flat loads, which also count against the LDS wait counter and turn every wait in the
+// prefetching loops into a full wait).
+#define LRE_GLOBAL __attribute__((address_space(1)))
+
+struct BInstG {
+  const LRE_GLOBAL uint16_t* counts;
+  LRE_GLOBAL double* coef;
+  LRE_GLOBAL char* rho;
+  uint64_t shots;
+  int64_t off_part, off_tmp;
+  int32_t n, q1;
+};
+
+__device__ __forceinline__ BInstG global_view(const BInst& I) {
+  BInstG G;
+  G.counts = (const LRE_GLOBAL uint16_t*)I.counts;
+  G.coef = (LRE_GLOBAL double*)I.coef;
+  G.rho = (LRE_GLOBAL char*)I.rho;
+  G.shots = I.shots;
+  G.off_part = I.off_part;
+  G.off_tmp = I.off_tmp;
+  G.n = I.n;
+  G.q1 = I.q1;
+  return G;
+}
 
 constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
 constexpr size_t kLdsCounts = (size_t)StreamGeom<kQ>::NACC * 4 + (size_t)StreamGeom<kQ>::NROWS * 4;
@@ -67,68 +95,89 @@ constexpr size_t kLdsRhoLow = 2 * (size_t)RhoLowLds<kJ>::SIZE * 8;
 constexpr size_t kLds = cmax(kLdsCounts, kLdsRhoLow);
 constexpr int64_t kRhoElemsPerBlock = 4096;  // step-(ii) high elements per unit of rho_blocks
 
+// The callees below take the instance with global-typed pointers; the generic pointers
+// they hand to the shared device functions are casts of them, from which the compiler
+// infers global loads and stores.
+__device__ __forceinline__ char* g2p(LRE_GLOBAL char* p) { return (char*)p; }
+
+template <int H, typename OutT>
+__device__ __forceinline__ void rho_high_loop(const double2* tmp, void* rho, int n, int64_t e0, int64_t e1, int tid) {
+#pragma unroll 4
+  for (int64_t t = e0 + tid; t < e1; t += kBT) rho_high_reg<H, OutT>(tmp, rho, n, kJ, t);
+}
+
 template <typename OutT>
-__device__ __forceinline__ void rho_high_range(const BInst& I, int64_t e0, int64_t e1, int tid, char* ws) {
-  const double2* tmp = reinterpret_cast<const double2*>(ws + I.off_tmp);
+__device__ __forceinline__ void rho_high_range(const BInstG& I, int64_t e0, int64_t e1, int tid, LRE_GLOBAL char* ws) {
+  const double2* tmp = reinterpret_cast<const double2*>(g2p(ws + I.off_tmp));
+  void* rho = (void*)g2p(I.rho);
   switch (I.n - kJ) {
-    case 1: for (int64_t t = e0 + tid; t < e1; t += kBT) rho_high_reg<1, OutT>(tmp, I.rho, I.n, kJ, t); break;
-    case 2: for (int64_t t = e0 + tid; t < e1; t += kBT) rho_high_reg<2, OutT>(tmp, I.rho, I.n, kJ, t); break;
-    default: for (int64_t t = e0 + tid; t < e1; t += kBT) rho_high_reg<3, OutT>(tmp, I.rho, I.n, kJ, t); break;
+    case 1: rho_high_loop<1, OutT>(tmp, rho, I.n, e0, e1, tid); break;
+    case 2: rho_high_loop<2, OutT>(tmp, rho, I.n, e0, e1, tid); break;
+    default: rho_high_loop<3, OutT>(tmp, rho, I.n, e0, e1, tid); break;
   }
 }
 
 // An instance with n <= 7 (one counts-pass tile) from counts to rho in one workgroup;
 // __syncthreads orders the phases (it is a workgroup-scope release/acquire).
-template <int Q, bool MAD24, bool PREFETCH, typename OutT>
-__device__ __forceinline__ void small_rho(const BInst& I, int tid, char* ws, double* re, double* im) {
+template <int Q, typename OutT>
+__device__ __forceinline__ void small_rho(const BInstG& I, int tid, LRE_GLOBAL char* ws, double* re, double* im) {
+  const double* coef = (const double*)I.coef;
   if constexpr (Q <= kJ) {
-    rho_low_block<Q, true, OutT, kBT>(I.coef, I.rho, I.n, 0, tid, re, im);
+    rho_low_block<Q, true, OutT, kBT>(coef, (void*)g2p(I.rho), I.n, 0, tid, re, im);
   } else {
-    for (int64_t a = 0; a < 4; ++a) {
-      rho_low6_block<kBT>(I.coef, reinterpret_cast<double2*>(ws + I.off_tmp), a, tid, re);
-      __syncthreads();
-    }
+    rho_low6_blocks<kBT>(coef, reinterpret_cast<double2*>(g2p(ws + I.off_tmp)), [](int z) { return (int64_t)z; },
+                         4, tid, re);
+    __syncthreads();
     rho_high_range<OutT>(I, 0, (int64_t)2 * 64 * 64, tid, ws);
   }
 }
 
 template <int Q, bool MAD24, bool PREFETCH>
-__device__ __noinline__ void run_small(const BInst& I, uint8_t var, int tid, char* ws, char* smem,
+__device__ __noinline__ void run_small(const BInstG& I, uint8_t var, int tid, LRE_GLOBAL char* ws, char* smem,
                                        uint32_t* flags) {
   uint32_t* acc = reinterpret_cast<uint32_t*>(smem);
   uint32_t* rs = acc + StreamGeom<Q>::NACC;
-  uint32_t* rowpart = reinterpret_cast<uint32_t*>(ws + I.off_rowpart);
-  counts_block<Q, kBT, uint32_t, false, Out::CoefUniform, MAD24, PREFETCH>(I.counts, I.n, 1, nullptr, I.coef,
-                                                                          rowpart, I.shots, 0, tid, acc, rs);
+  counts_block<Q, kBT, uint32_t, false, Out::CoefUniform, MAD24, PREFETCH>(
+      (const uint16_t*)I.counts, I.n, 1, nullptr, (void*)(double*)I.coef, nullptr, I.shots, 0, tid, acc, rs, flags);
   __syncthreads();
-  const int64_t rows = ipow3(Q);
-  for (int64_t b = tid; b < rows; b += kBT) check_row(rowpart, rows, 1, nullptr, I.shots, b, flags);
   if (var & V_RHO) {
     double* re = reinterpret_cast<double*>(smem);
     double* im = re + (kLds / 16);
-    if (var & V_FP32) small_rho<Q, MAD24, PREFETCH, float>(I, tid, ws, re, im);
-    else small_rho<Q, MAD24, PREFETCH, double>(I, tid, ws, re, im);
+    if (var & V_FP32) small_rho<Q, float>(I, tid, ws, re, im);
+    else small_rho<Q, double>(I, tid, ws, re, im);
   }
 }
 
+// Row groups [g0, g1) (3^7 rows each): one block call per group covering all 2^(n-7)
+// outcome tiles of its rows, so the row totals are complete and checked in the block.
 template <bool MAD24, bool PREFETCH>
-__device__ __noinline__ void run_counts(const BInst& I, int64_t b0, int64_t b1, int tid, char* ws, char* smem) {
+__device__ __noinline__ void run_counts(const BInstG& I, int64_t g0, int64_t g1, int tid, LRE_GLOBAL char* ws,
+                                        char* smem, uint32_t* flags) {
   uint32_t* acc = reinterpret_cast<uint32_t*>(smem);
   uint32_t* rs = acc + StreamGeom<kQ>::NACC;
-  uint32_t* rowpart = reinterpret_cast<uint32_t*>(ws + I.off_rowpart);
-  for (int64_t blk = b0; blk < b1; ++blk) {
-    counts_block<kQ, kBT, uint32_t, false, Out::Partial, MAD24, PREFETCH>(I.counts, I.n, 1, nullptr, ws + I.off_part,
-                                                                         rowpart, I.shots, blk, tid, acc, rs);
-    __syncthreads();  // the next tile clears the LDS this one still reads
+  void* part = (void*)g2p(ws + I.off_part);
+  const uint16_t* counts = (const uint16_t*)I.counts;
+  const int chunks = 1 << (I.n - kQ);
+  for (int64_t g = g0; g < g1; ++g) {
+    counts_block<kQ, kBT, uint32_t, false, Out::Partial, MAD24, PREFETCH>(counts, I.n, chunks, nullptr, part, nullptr,
+                                                                         I.shots, g, tid, acc, rs, flags);
+    __syncthreads();  // the next group clears the LDS this one still reads
   }
 }
 
-__device__ __noinline__ void run_fold(const BInst& I, int64_t c0, int64_t c1, int tid, char* ws) {
-  const uint32_t* in = reinterpret_cast<const uint32_t*>(ws + I.off_part);
+__device__ __noinline__ void run_fold(const BInstG& I, int64_t c0, int64_t c1, int tid, LRE_GLOBAL char* ws) {
+  const uint32_t* in = reinterpret_cast<const uint32_t*>(g2p(ws + I.off_part));
+  double* coef = (double*)I.coef;
   const int h = I.n - kQ;
-  for (int64_t col = c0 + tid; col < c1; col += kBT) {
-    if (h == 1) fold_partial_col<1, uint32_t, uint32_t, Out::CoefUniform>(in, I.coef, I.n, h, kQ, I.shots, col);
-    else fold_partial_col<2, uint32_t, uint32_t, Out::CoefUniform>(in, I.coef, I.n, h, kQ, I.shots, col);
+  // four columns per thread at a time, so that their loads are in flight together
+  if (h == 1) {
+#pragma unroll 4
+    for (int64_t col = c0 + tid; col < c1; col += kBT)
+      fold_partial_col<1, uint32_t, uint32_t, Out::CoefUniform>(in, coef, I.n, h, kQ, I.shots, col);
+  } else {
+#pragma unroll 4
+    for (int64_t col = c0 + tid; col < c1; col += kBT)
+      fold_partial_col<2, uint32_t, uint32_t, Out::CoefUniform>(in, coef, I.n, h, kQ, I.shots, col);
   }
 }
 
@@ -137,26 +186,30 @@ __device__ __noinline__ void run_fold(const BInst& I, int64_t c0, int64_t c1, in
 // intermediate), then the high transform of the 4^6 (r_lo, x_lo) entries of each x_hi
 // row group -- both inside this workgroup, ordered by barriers.
 template <typename OutT>
-__device__ __noinline__ void run_rho(const BInst& I, int64_t x0, int64_t x1, int tid, char* ws, char* smem) {
+__device__ __noinline__ void run_rho(const BInstG& I, int64_t x0, int64_t x1, int tid, LRE_GLOBAL char* ws,
+                                     char* smem) {
   double* re = reinterpret_cast<double*>(smem);
-  double* im = re + (kLds / 16);
+  const double* coef = (const double*)I.coef;
+  double2* tmp = reinterpret_cast<double2*>(g2p(ws + I.off_tmp));
   const int H = I.n - kJ;
   for (int64_t xh = x0; xh < x1; ++xh) {
-    for (int z = 0; z < (1 << H); ++z) {
+    auto a_of = [&](int z) {
       int64_t a_hi = 0;
       for (int p = H - 1; p >= 0; --p) {
         const int xb = (int)(xh >> p) & 1, zb = (z >> p) & 1;
         a_hi = a_hi * 4 + (xb ? (zb ? 2 : 1) : (zb ? 3 : 0));
       }
-      rho_low6_block<kBT>(I.coef, reinterpret_cast<double2*>(ws + I.off_tmp), a_hi, tid, re);
-      __syncthreads();
-    }
+      return a_hi;
+    };
+    rho_low6_blocks<kBT>(coef, tmp, a_of, 1 << H, tid, re);
+    __syncthreads();
     rho_high_range<OutT>(I, xh * kRhoElemsPerBlock, (xh + 1) * kRhoElemsPerBlock, tid, ws);
+    __syncthreads();
   }
 }
 
 template <bool PREFETCH>
-__device__ __forceinline__ void dispatch_small(const BInst& I, uint8_t var, int tid, char* ws, char* smem,
+__device__ __forceinline__ void dispatch_small(const BInstG& I, uint8_t var, int tid, LRE_GLOBAL char* ws, char* smem,
                                                uint32_t* flags) {
   switch (I.n) {
     case 1: run_small<1, false, PREFETCH>(I, var, tid, ws, smem, flags); break;
@@ -177,13 +230,14 @@ __device__ __forceinline__ void dispatch_small(const BInst& I, uint8_t var, int 
 // row prefetch; two: no prefetch, 128 registers).
 template <int WORKERS>
 __global__ __launch_bounds__(kBT, WORKERS == 2 ? 4 : 1) void batch_kernel(
-    const BItem* __restrict__ items, int nitems, const BInst* __restrict__ insts, char* __restrict__ ws,
+    const BItem* __restrict__ items, int nitems, const BInst* __restrict__ insts, char* __restrict__ ws_arg,
     uint32_t* __restrict__ ctl, uint32_t* __restrict__ flags) {
   constexpr bool PF = WORKERS == 1;
   __shared__ __align__(16) char smem[kLds];
   __shared__ int s_item;
   __shared__ int s_skip;
   const int tid = threadIdx.x;
+  LRE_GLOBAL char* ws = (LRE_GLOBAL char*)ws_arg;
   for (;;) {
     if (tid == 0) s_item = (int)atomicAdd(&ctl[0], 1u);
     __syncthreads();
@@ -209,20 +263,13 @@ __global__ __launch_bounds__(kBT, WORKERS == 2 ? 4 : 1) void batch_kernel(
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       if (s_skip) continue;  // uniform: the skipped item's counter never moves, its consumers time out too
     }
-    const BInst I = insts[W.inst];
+    const BInstG I = global_view(insts[W.inst]);
     switch (W.kind) {
       case K_SMALL: dispatch_small<PF>(I, W.variant, tid, ws, smem, flags); break;
       case K_COUNTS:
-        if (W.variant & V_MAD24) run_counts<true, PF>(I, W.begin, W.end, tid, ws, smem);
-        else run_counts<false, PF>(I, W.begin, W.end, tid, ws, smem);
+        if (W.variant & V_MAD24) run_counts<true, PF>(I, W.begin, W.end, tid, ws, smem, flags);
+        else run_counts<false, PF>(I, W.begin, W.end, tid, ws, smem, flags);
         break;
-      case K_CHECK: {
-        const int64_t rows = ipow3(I.q1);
-        const int64_t runs = (int64_t)1 << (I.n - I.q1);
-        const uint32_t* rowpart = reinterpret_cast<const uint32_t*>(ws + I.off_rowpart);
-        for (int64_t b = W.begin + tid; b < W.end; b += kBT) check_row(rowpart, rows, runs, nullptr, I.shots, b, flags);
-        break;
-      }
       case K_FOLD: run_fold(I, W.begin, W.end, tid, ws); break;
       default:
         if (W.variant & V_FP32) run_rho<float>(I, W.begin, W.end, tid, ws, smem);
@@ -311,15 +358,12 @@ void emit_stage(const lre_batch& B, int j, int stage, std::vector<BItem>& out, S
     return;
   }
   switch (stage) {
-    case 0:
-      add_range(out, j, K_COUNTS, mad, m.blocks1, t.counts_tiles, -1, 0, c_counts, &sc.counts);
+    case 0:  // row groups of 3^7 bases, each with all its outcome tiles
+      add_range(out, j, K_COUNTS, mad, ipow3(m.n - kQ), t.counts_tiles, -1, 0, c_counts, &sc.counts);
       break;
-    case 1: {
-      const int64_t nb = ipow3(m.n);
-      add_range(out, j, K_CHECK, 0, nb, nb, c_counts, sc.counts, -1, nullptr);
+    case 1:
       add_range(out, j, K_FOLD, 0, ipow4(kQ), t.fold_cols, c_counts, sc.counts, want_rho ? c_fold : -1, &sc.fold);
       break;
-    }
     case 2:
       if (want_rho)
         add_range(out, j, K_RHO, fp32, (int64_t)1 << (m.n - kJ), t.rho_blocks, c_fold, sc.fold, -1, nullptr);
@@ -418,8 +462,6 @@ lre_status lre_batch_plan(lre_ctx* ctx, const lre_instance* inst, int count, uin
       d.off_part = (int64_t)off;
       off += align256((size_t)m.blocks1 * (size_t)ipow4(kQ) * 4);
     }
-    d.off_rowpart = (int64_t)off;
-    off += align256((size_t)m.blocks1 * (size_t)ipow3(m.q1) * 4);
     d.off_tmp = 0;
     if (want_rho && I.n > kJ) {
       d.off_tmp = (int64_t)off;

@@ -399,10 +399,13 @@ __device__ __forceinline__ uint32_t stream_slot(uint32_t a) {
 // acc / rs_acc: LDS of NACC accumulators and NROWS row totals.  Every thread of the
 // block calls this (it synchronises the block).
 template <int Q, int THREADS, typename Acc, bool PER_BASIS, Out MODE, bool MAD24, bool PREFETCH = PER_BASIS>
+// check_flags (uniform shots, blocks that cover whole rows, i.e. chunks == 2^(n-Q)): check
+// the row totals against `shots` in the block instead of writing rowpart.
 __device__ __forceinline__ void counts_block(const uint16_t* __restrict__ counts, int n, int chunks,
                                              const double* __restrict__ inv_nb, void* __restrict__ out,
                                              uint32_t* __restrict__ rowpart, uint64_t shots, int64_t blk,
-                                             int tid, Acc* __restrict__ acc, uint32_t* __restrict__ rs_acc) {
+                                             int tid, Acc* __restrict__ acc, uint32_t* __restrict__ rs_acc,
+                                             uint32_t* __restrict__ check_flags = nullptr) {
   using G = StreamGeom<Q>;
   constexpr int GROUPS = THREADS / G::LPC;
   constexpr int LB = G::LB;
@@ -542,11 +545,12 @@ __device__ __forceinline__ void counts_block(const uint16_t* __restrict__ counts
         }
       };
       // Steps are numbered s = 3 rs + d2 (243 per tile for Q = 7); group g takes the
-      // contiguous range [s0, s1).  A range may start or end inside a row-set: the
-      // qubit-2 identity sums are then flushed as partial sums, which the LDS adds.
-      constexpr int TOTAL = G::NRS * 3;
-      const int s0 = (int)(((int64_t)grp * TOTAL) / GROUPS);
-      const int s1 = (int)(((int64_t)(grp + 1) * TOTAL) / GROUPS);
+      // steps of a contiguous range of whole row-sets, so that the groups of a wave reach
+      // the end of a row-set together.  (The step loop also handles a range that starts
+      // or ends inside a row-set: the qubit-2 identity sums are then flushed as partial
+      // sums, which the LDS adds.)
+      const int s0 = 3 * (int)(((int64_t)grp * G::NRS) / GROUPS);
+      const int s1 = 3 * (int)(((int64_t)(grp + 1) * G::NRS) / GROUPS);
       if constexpr (PREFETCH) {
         // Double-buffered: the next step's rows are in flight while this one is folded.
         // The prefetch is unconditional (past the last step it is a cached dummy read) so
@@ -632,8 +636,14 @@ __device__ __forceinline__ void counts_block(const uint16_t* __restrict__ counts
     __syncthreads();
   }
 
-  uint32_t* __restrict__ rp = rowpart + blk * G::NROWS;
-  for (int i = tid; i < G::NROWS; i += THREADS) rp[i] = rs_acc[i];
+  if (check_flags) {
+    // The block covered every outcome of its rows: check the totals here (uniform shots).
+    for (int i = tid; i < G::NROWS; i += THREADS)
+      if (rs_acc[i] != (uint32_t)shots) atomicOr(check_flags, (uint32_t)FLAG_SHOTS);
+  } else {
+    uint32_t* __restrict__ rp = rowpart + blk * G::NROWS;
+    for (int i = tid; i < G::NROWS; i += THREADS) rp[i] = rs_acc[i];
+  }
 }
 
 template <int Q, int THREADS, typename Acc, bool PER_BASIS, Out MODE, bool MAD24, int MINWAVES = 1,
@@ -1012,15 +1022,22 @@ static __global__ void reciprocal_kernel(const uint32_t* __restrict__ nb, double
 }
 
 // rowpart as written by fold_counts_kernel: [3^n / rows][runs][rows].
-__device__ __forceinline__ void check_row(const uint32_t* __restrict__ rowpart, int64_t rows, int64_t runs,
-                                          const uint32_t* __restrict__ nb, uint64_t shots, int64_t b,
-                                          uint32_t* __restrict__ flags) {
-  const int64_t grp = b / rows, j = b % rows;
+// Basis b = grp * rows + j of row group grp.
+__device__ __forceinline__ void check_row_gj(const uint32_t* __restrict__ rowpart, int64_t rows, int64_t runs,
+                                             const uint32_t* __restrict__ nb, uint64_t shots, int64_t grp, int64_t j,
+                                             uint32_t* __restrict__ flags) {
+  const int64_t b = grp * rows + j;
   uint64_t tot = 0;
   for (int64_t r = 0; r < runs; ++r) tot += rowpart[(grp * runs + r) * rows + j];
   const uint64_t want = shots ? shots : (uint64_t)nb[b];
   if (tot != want) atomicOr(flags, (uint32_t)FLAG_SHOTS);
   if (!shots && want == 0) atomicOr(flags, (uint32_t)FLAG_EMPTY);
+}
+
+__device__ __forceinline__ void check_row(const uint32_t* __restrict__ rowpart, int64_t rows, int64_t runs,
+                                          const uint32_t* __restrict__ nb, uint64_t shots, int64_t b,
+                                          uint32_t* __restrict__ flags) {
+  check_row_gj(rowpart, rows, runs, nb, shots, b / rows, b % rows, flags);
 }
 
 static __global__ void check_rows_kernel(const uint32_t* __restrict__ rowpart, int64_t rows, int64_t runs,
@@ -1220,6 +1237,39 @@ __device__ __forceinline__ uint32_t spread6(uint32_t v) {
 // gathers its 16 values z = zl + 4k (letter digit x_p ^ 3 z_p: I, X, Y, Z for (x, z)
 // bits (0,0), (1,0), (1,1), (0,1)), transforms z bits 2-5 in registers and bits 0-1
 // across its lane quad (DPP, exact butterflies), and writes tmp[a_hi][r][x].
+// Transform part: blk (LDS) holds the 4096 coefficients of block a_hi; threads 0..255.
+__device__ __forceinline__ void rho_low6_from_lds(const double* __restrict__ blk, double2* __restrict__ tmp,
+                                                  int64_t a_hi, int t) {
+  const uint32_t x = (uint32_t)t >> 2, zl = (uint32_t)t & 3u;
+  const uint32_t sx = spread6(x);
+  double re[16], im[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const uint32_t z = zl + 4u * (uint32_t)k;
+    const uint32_t sz = spread6(z);
+    re[k] = blk[sx ^ sz ^ (sz << 1)];
+    im[k] = 0.0;
+    mul_neg_i_pow(__popc(x & z), re[k], im[k]);
+  }
+  wht_regs<4>(re);
+  wht_regs<4>(im);
+  int32_t sg[2] = {(t & 1) ? -1 : 1, (t & 2) ? -1 : 1};
+  asm volatile("" : "+v"(sg[0]), "+v"(sg[1]));
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    lane_bfly<kDppQuadXor1, false>(re[k], sg[0]);
+    lane_bfly<kDppQuadXor1, false>(im[k], sg[0]);
+  }
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    lane_bfly<kDppQuadXor2, false>(re[k], sg[1]);
+    lane_bfly<kDppQuadXor2, false>(im[k], sg[1]);
+  }
+  double2* __restrict__ o = tmp + a_hi * 4096;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) o[(zl + 4u * (uint32_t)k) * 64u + x] = make_double2(re[k], im[k]);
+}
+
 // blk: LDS of 4096 doubles.  Every thread of the block calls this (it synchronises);
 // threads 0..255 do the transform, the caller synchronises before reusing blk.
 template <int THREADS>
@@ -1229,35 +1279,36 @@ __device__ __forceinline__ void rho_low6_block(const double* __restrict__ coef, 
   const double* __restrict__ e = coef + a_hi * 4096;
   for (int i = t; i < 4096; i += THREADS) blk[i] = e[i];
   __syncthreads();
-  if (t < 256) {
-    const uint32_t x = (uint32_t)t >> 2, zl = (uint32_t)t & 3u;
-    const uint32_t sx = spread6(x);
-    double re[16], im[16];
+  if (t < 256) rho_low6_from_lds(blk, tmp, a_hi, t);
+}
+
+// nz blocks a_hi = a_of(0 .. nz-1) in sequence, the next block's coefficients loaded into
+// registers while the current one is transformed.
+template <int THREADS, typename AOf>
+__device__ __forceinline__ void rho_low6_blocks(const double* __restrict__ coef, double2* __restrict__ tmp,
+                                                AOf a_of, int nz, int t, double* __restrict__ blk) {
+  constexpr int PER = (4096 + THREADS - 1) / THREADS;
+  static_assert(THREADS >= 256, "one thread per (x, z quad)");
+  double pre[PER];
+  {
+    const double* __restrict__ e = coef + a_of(0) * 4096;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const uint32_t z = zl + 4u * (uint32_t)k;
-      const uint32_t sz = spread6(z);
-      re[k] = blk[sx ^ sz ^ (sz << 1)];
-      im[k] = 0.0;
-      mul_neg_i_pow(__popc(x & z), re[k], im[k]);
+    for (int i = 0; i < PER; ++i)
+      if (t + THREADS * i < 4096) pre[i] = e[t + THREADS * i];
+  }
+  for (int z = 0; z < nz; ++z) {
+    __syncthreads();  // the previous block's transform has read blk
+#pragma unroll
+    for (int i = 0; i < PER; ++i)
+      if (t + THREADS * i < 4096) blk[t + THREADS * i] = pre[i];
+    __syncthreads();
+    if (z + 1 < nz) {
+      const double* __restrict__ e = coef + a_of(z + 1) * 4096;
+#pragma unroll
+      for (int i = 0; i < PER; ++i)
+        if (t + THREADS * i < 4096) pre[i] = e[t + THREADS * i];
     }
-    wht_regs<4>(re);
-    wht_regs<4>(im);
-    int32_t sg[2] = {(t & 1) ? -1 : 1, (t & 2) ? -1 : 1};
-    asm volatile("" : "+v"(sg[0]), "+v"(sg[1]));
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      lane_bfly<kDppQuadXor1, false>(re[k], sg[0]);
-      lane_bfly<kDppQuadXor1, false>(im[k], sg[0]);
-    }
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      lane_bfly<kDppQuadXor2, false>(re[k], sg[1]);
-      lane_bfly<kDppQuadXor2, false>(im[k], sg[1]);
-    }
-    double2* __restrict__ o = tmp + a_hi * 4096;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) o[(zl + 4u * (uint32_t)k) * 64u + x] = make_double2(re[k], im[k]);
+    if (t < 256) rho_low6_from_lds(blk, tmp, a_of(z), t);
   }
 }
 

@@ -65,8 +65,8 @@ def test_batch_matches_single_and_oracle():
     b.close()
 
 
-@pytest.mark.parametrize("tiles", [(1, 1, 512, 1, 0), (2, 4, 512 * 16, 16, 1), (1, 3, 512 * 5, 7, 1),
-                                   (2, 1, 512, 8, 0)])
+@pytest.mark.parametrize("tiles", [(1, 1, 432, 1, 0), (2, 4, 432 * 16, 16, 1), (1, 3, 432 * 5, 7, 1),
+                                   (2, 1, 432, 8, 0)])
 def test_batch_tile_shapes(tiles):
     print(f"[batch tiles {tiles}]", flush=True)
     counts, shots = _instances(12, [9, 4, 8, 7, 1, 9, 6, 5])
