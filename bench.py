@@ -113,6 +113,20 @@ def make_workload(name, torch):
     raise SystemExit(f"unknown workload {name}")
 
 
+def host_cpu():
+    """Model name and logical CPU count of the host the oracle runs on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count()}
+
+
 def cpu_baseline(workload, n, shots, counts_dev, coef_dev, budget_s=12.0):
     """Time the CPU oracle (as it stands) on a bounded sample of the same workload and
     extrapolate to the whole step: step (i) visits 12^n (projector, coefficient) terms,
@@ -168,7 +182,7 @@ def cpu_baseline(workload, n, shots, counts_dev, coef_dev, budget_s=12.0):
         t_full += 8.0 ** n / (visits_ii / t_ii)
     else:
         t_full += 8.0 ** n / rate_i  # same inner-loop cost per visited term
-    return {"value": 6.0 ** n / t_full, "unit": "counts/s", "cores": threads, "kind": "oracle",
+    return {"value": 6.0 ** n / t_full, "unit": "counts/s", "cores": threads, "kind": "oracle", "host": host_cpu(),
             "sample": f"{sample}; oracle time {t_i + t_ii:.1f} s, extrapolated to the whole "
                       f"step ({t_full / 3600:.3g} h for 12^n + 8^n terms)"}
 
@@ -278,6 +292,7 @@ def bench_batch(args, torch, lre):
         t_full = sum(12.0 ** n + 8.0 ** n for n in ns) / rate
         out["cpu_baseline"] = {"value": n_counts / t_full, "unit": "counts/s",
                                "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count())), "kind": "oracle",
+                               "host": host_cpu(),
                                "sample": f"full oracle (coef + rho) on {done} randomly chosen instances "
                                          f"({t_cpu:.1f} s), extrapolated by 12^n + 8^n terms to all 512 "
                                          f"({t_full:.0f} s)"}
@@ -399,7 +414,10 @@ def main():
     if other is not None:
         mfma, plain = (head, other) if head_flags else (other, head)
         mean = lambda v: sum(v) / len(v)
+        # int8 work of the MFMA form: H_64 on two byte limbs = 64 multiply-adds per limb per count
+        mfma_tops = 2.0 * 64 * 2 * n_counts / (mean(mfma["pass1"]) / 1e3) / 1e12
         out["mfma_vs_plain"] = {
+            "mfma_int8_tops": mfma_tops, "mfma_int8_peak_tops": 5000.0, "mfma_frac": mfma_tops / 5000.0,
             "counts_pass_speedup": mean(plain["pass1"]) / mean(mfma["pass1"]),
             "step_speedup": plain["ms_step"] / mfma["ms_step"],
             "plain_counts_pass_ms": mean(plain["pass1"]), "mfma_counts_pass_ms": mean(mfma["pass1"]),

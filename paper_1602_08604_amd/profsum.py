@@ -1,6 +1,7 @@
 """Summaries of rocprofv3 output for the committed profile records.
 
     python -m paper_1602_08604_amd.profsum stats   --dir D --out F.txt --command CMD
+    python -m paper_1602_08604_amd.profsum counters --dirs D... --commands CMD... --kernel REGEX --out F.txt
     python -m paper_1602_08604_amd.profsum traffic --fetch-dir D1 --write-dir D2 \
         --kernel REGEX --copy-kernel REGEX --copy-bytes B --out-json F.json --out-txt F.txt \
         --command-fetch CMD1 --command-write CMD2
@@ -128,9 +129,40 @@ def traffic(args):
     print("\n".join(lines))
 
 
+def counters(args):
+    """Mean per dispatch of every counter in the runs, for the kernels matching --kernel."""
+    lines = [f"# rocprofv3 counters of kernels matching {args.kernel!r}", ""]
+    for d, cmd in zip(args.dirs, args.commands):
+        lines.append(f"run: {cmd}")
+        per = {}
+        for r in csv.DictReader(open(_find(d, "counter_collection.csv"))):
+            name = short_name(r["Kernel_Name"])
+            if not re.search(args.kernel, name):
+                continue
+            key = (name, r["Counter_Name"], r.get("Dispatch_Id", ""))
+            per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+        agg = {}
+        for (name, ctr, _), v in per.items():
+            agg.setdefault((name, ctr), []).append(v)
+        for (name, ctr), v in sorted(agg.items()):
+            lines.append(f"  {name[:60]:60s} {ctr:28s} {statistics.mean(v):16.6g} (x{len(v)})")
+        lines.append("")
+    if args.note:
+        lines.append(args.note)
+    with open(args.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("--dirs", nargs="+", required=True)
+    c.add_argument("--commands", nargs="+", required=True)
+    c.add_argument("--kernel", required=True)
+    c.add_argument("--out", required=True)
+    c.add_argument("--note", default="")
     s = sub.add_parser("stats")
     s.add_argument("--dir", required=True)
     s.add_argument("--out", required=True)
@@ -149,7 +181,7 @@ def main():
     t.add_argument("--command-fetch", required=True)
     t.add_argument("--command-write", required=True)
     a = ap.parse_args()
-    stats(a) if a.cmd == "stats" else traffic(a)
+    {"stats": stats, "traffic": traffic, "counters": counters}[a.cmd](a)
 
 
 if __name__ == "__main__":
