@@ -382,16 +382,30 @@ struct StreamGeom {
 // For 4 lane qubits the top letter (bits 6-7) is also folded into the low bits (a
 // bijection), which spreads the 16 lanes of a group and the 4 groups of a wave over
 // more banks (fewer passes per binary64 atomic; modelled on the host).
+// Both maps below are linear over XOR (for u < 256, (u >> 6) * 9 = h | h << 3 with
+// h = u >> 6 only touches bits 0-4), so the slot splits as
+//   slot = slot_fold(alane) ^ slot_key(areg):
+// the lane part is set once per row-set and every emission (areg a compile-time
+// constant, or a constant XOR one runtime digit) costs one XOR.
 template <int Q, int LB>
-__device__ __forceinline__ uint32_t stream_slot_of(uint32_t areg, uint32_t alane) {
-  constexpr uint32_t hmask = (1u << (2 * (Q - LB))) - 1;
-  uint32_t u = alane ^ (areg & hmask);
-  if constexpr (Q - LB == 4) u = (u & 0xC0u) | ((u ^ ((u >> 6) * 9u)) & 0x3Fu);
-  return (areg << (2 * (Q - LB))) | u;
+__host__ __device__ constexpr uint32_t slot_fold(uint32_t u) {
+  if constexpr (Q - LB == 4) return u ^ ((u >> 6) * 9u);
+  else return u;
 }
 
 template <int Q, int LB>
-__device__ __forceinline__ uint32_t stream_slot(uint32_t a) {
+__host__ __device__ constexpr uint32_t slot_key(uint32_t areg) {
+  constexpr uint32_t hmask = (1u << (2 * (Q - LB))) - 1;
+  return (areg << (2 * (Q - LB))) ^ slot_fold<Q, LB>(areg & hmask);
+}
+
+template <int Q, int LB>
+__host__ __device__ constexpr uint32_t stream_slot_of(uint32_t areg, uint32_t alane) {
+  return slot_fold<Q, LB>(alane) ^ slot_key<Q, LB>(areg);
+}
+
+template <int Q, int LB>
+__host__ __device__ constexpr uint32_t stream_slot(uint32_t a) {
   return stream_slot_of<Q, LB>(a & ((1u << (2 * LB)) - 1), a >> (2 * LB));
 }
 
@@ -448,7 +462,7 @@ __device__ __forceinline__ void counts_block(const uint16_t* __restrict__ counts
       Acc L1[4][2], L2[4][4];
 #pragma unroll
       for (int a = 0; a < 4; ++a) { L1[a][0] = L1[a][1] = Acc(0); L2[a][0] = L2[a][1] = L2[a][2] = L2[a][3] = Acc(0); }
-      uint32_t ulane = 0;
+      uint32_t ubase = 0;   // slot_fold(lane letters) * sizeof(Acc): byte offset of the lane part
       // dummy: a prefetch past the group's last step reads the tile's first row segment
       // nine times (cached) instead of fresh rows.
       auto load9 = [&](uint32_t (&buf)[9][4], double& invr, int rs, int d2, bool dummy = false)
@@ -461,18 +475,24 @@ __device__ __forceinline__ void counts_block(const uint16_t* __restrict__ counts
         if constexpr (PER_BASIS && G::LPC >= 9) invr = inv_nb[row0 + rr + (lam < 9 ? lam : 0)];  // lane r: row r
       };
       // Four emissions at once: lane butterflies interleaved, then the four LDS adds.
-      auto emit4 = [&](Acc (&v)[4], const uint32_t (&areg)[4]) __attribute__((always_inline)) {
+      // base: ubase, possibly XORed with the key of a runtime digit; areg: constants.
+      auto emit4 = [&](Acc (&v)[4], const uint32_t (&areg)[4], uint32_t base) __attribute__((always_inline)) {
         wht_lanes_n<G::LL, MAD24, 4>(v, sg);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) atomicAdd(&acc[stream_slot_of<Q, LB>(areg[j], ulane)], v[j]);
+        for (int j = 0; j < 4; ++j)
+          atomicAdd(reinterpret_cast<Acc*>(reinterpret_cast<char*>(acc) +
+                                           (base ^ (slot_key<Q, LB>(areg[j]) * (uint32_t)sizeof(Acc)))),
+                    v[j]);
       };
       // first: the group's first step (its row-set's letters are not yet set up);
       // last: the group's last step (flush the qubit-2 identity sums even mid row-set).
       auto step = [&](const uint32_t (&raw)[9][4], double invr, int rs, int d2, bool first,
                       bool last) __attribute__((always_inline)) {
-        if (first || d2 == 0) ulane = ulane_of(rs);
+        if (first || d2 == 0) ubase = slot_fold<Q, LB>(ulane_of(rs)) * (uint32_t)sizeof(Acc);
         const int rr = rs * G::NSEQ + 9 * d2;
-        const uint32_t a2 = 16u * (uint32_t)(d2 + 1);
+        // Letter d2 + 1 of qubit 2 (bits 4-5 of the register letters) in every emission
+        // of this step except the qubit-2 identity ones.
+        const uint32_t b2 = ubase ^ (slot_key<Q, LB>(16u * (uint32_t)(d2 + 1)) * (uint32_t)sizeof(Acc));
         StaticFor<0, 3>::run([&](auto d1c) __attribute__((always_inline)) {
           constexpr int d1 = decltype(d1c)::value;
           Acc L0[4] = {Acc(0), Acc(0), Acc(0), Acc(0)};
@@ -516,21 +536,20 @@ __device__ __forceinline__ void counts_block(const uint16_t* __restrict__ counts
             else if (m2 == 0) L2[0][d1 + 1] += L0[mr];
             else pend[3] = L0[mr];
           }
-          const uint32_t ar[4] = {1u + 4u * (d1 + 1) + a2, 2u + 4u * (d1 + 1) + a2, 3u + 4u * (d1 + 1) + a2,
-                                  4u * (d1 + 1) + a2};
-          emit4(pend, ar);
+          const uint32_t ar[4] = {1u + 4u * (d1 + 1), 2u + 4u * (d1 + 1), 3u + 4u * (d1 + 1), 4u * (d1 + 1)};
+          emit4(pend, ar, b2);
         });
         // End of the qubit-1 walk (letters of qubit 1 now final).
         {
           Acc v1[4];
-          const uint32_t ar[4] = {0u + a2, 1u + a2, 2u + a2, 3u + a2};
+          const uint32_t ar[4] = {0u, 1u, 2u, 3u};
 #pragma unroll
           for (int a0 = 0; a0 < 4; ++a0) {
             L2[a0][0] += L1[a0][0];
             v1[a0] = L1[a0][1];
             L1[a0][0] = L1[a0][1] = Acc(0);
           }
-          emit4(v1, ar);
+          emit4(v1, ar, b2);
         }
         if (d2 == 2 || last) {
           // End of the qubit-2 walk (or of this group's part of it): identity letter at qubit 2.
@@ -538,7 +557,7 @@ __device__ __forceinline__ void counts_block(const uint16_t* __restrict__ counts
           for (int a1 = 0; a1 < 4; ++a1) {
             Acc v2[4] = {L2[0][a1], L2[1][a1], L2[2][a1], L2[3][a1]};
             const uint32_t ar[4] = {0u + 4u * a1, 1u + 4u * a1, 2u + 4u * a1, 3u + 4u * a1};
-            emit4(v2, ar);
+            emit4(v2, ar, ubase);
 #pragma unroll
             for (int a0 = 0; a0 < 4; ++a0) L2[a0][a1] = Acc(0);
           }
