@@ -98,6 +98,15 @@ struct StaticFor {
   }
 };
 
+// Workgroup barrier that orders LDS accesses only.  __syncthreads() also fences global
+// memory, which makes every wave wait for all of its outstanding loads (prefetches
+// included) at the barrier.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // ---------------------------------------------------------------------------------
 // Walsh-Hadamard butterflies.  Natural order: after the transform element m holds
 // sum_s x_s (-1)^{popcount(s & m)}.
@@ -453,6 +462,16 @@ __device__ __forceinline__ void counts_block(const uint16_t* __restrict__ counts
     return u;
   };
 
+  // Carry: every group walks the same number of steps, so the prefetch issued by a
+  // group's last step of one tile can fetch its first step of the next tile (same rows,
+  // the next 2^Q outcomes): the loads stay in flight across the write-out.  With an odd
+  // step count that prefetch lands in the second buffer and moves to the first one at
+  // the next tile.
+  constexpr bool kCarry = LB == 3 && PREFETCH && G::NRS % GROUPS == 0;
+  constexpr bool kOddSteps = ((3 * G::NRS / GROUPS) & 1) == 1;
+  uint32_t bufA[9][4], bufB[9][4];
+  double invA = 0.0, invB = 0.0;
+
   for (int c = 0; c < chunks; ++c) {
     const int64_t s_hi = s_hi0 + c;
     const uint16_t* __restrict__ cchunk = counts + row0 * rowlen + (s_hi << Q) + lam * G::V;
@@ -465,10 +484,11 @@ __device__ __forceinline__ void counts_block(const uint16_t* __restrict__ counts
       uint32_t ubase = 0;   // slot_fold(lane letters) * sizeof(Acc): byte offset of the lane part
       // dummy: a prefetch past the group's last step reads the tile's first row segment
       // nine times (cached) instead of fresh rows.
-      auto load9 = [&](uint32_t (&buf)[9][4], double& invr, int rs, int d2, bool dummy = false)
-                       __attribute__((always_inline)) {
+      // next_tile: rows of step (rs, d2) in the next tile (2^Q outcomes further on).
+      auto load9 = [&](uint32_t (&buf)[9][4], double& invr, int rs, int d2, bool dummy = false,
+                       bool next_tile = false) __attribute__((always_inline)) {
         const int rr = dummy ? 0 : rs * G::NSEQ + 9 * d2;
-        const uint16_t* __restrict__ p = cchunk + (int64_t)rr * rowlen;
+        const uint16_t* __restrict__ p = cchunk + (int64_t)rr * rowlen + (next_tile ? (1 << Q) : 0);
         const int64_t stride = dummy ? 0 : rowlen;
 #pragma unroll
         for (int r = 0; r < 9; ++r) load_raw<8>(p + (int64_t)r * stride, buf[r]);
@@ -574,9 +594,37 @@ __device__ __forceinline__ void counts_block(const uint16_t* __restrict__ counts
         // Double-buffered: the next step's rows are in flight while this one is folded.
         // The prefetch is unconditional (past the last step it is a cached dummy read) so
         // that the wait for the current buffer never has to cover it.
-        uint32_t bufA[9][4], bufB[9][4];
-        double invA = 0.0, invB = 0.0;
-        if (s0 < s1) {
+        if constexpr (kCarry) {
+          // NST steps per group, known at compile time, so the buffer that receives the
+          // next tile's rows is known statically too.
+          constexpr int NST = 3 * G::NRS / GROUPS;
+          const bool carry = c + 1 < chunks;   // else the last prefetch is a dummy
+          if (c == 0) {
+            load9(bufA, invA, s0 / 3, s0 % 3);
+          } else if constexpr (kOddSteps) {
+#pragma unroll
+            for (int r = 0; r < 9; ++r)
+#pragma unroll
+              for (int k = 0; k < 4; ++k) bufA[r][k] = bufB[r][k];
+            invA = invB;
+          }
+          int s = s0;
+#pragma unroll 1
+          for (int i = 0; i + 1 < NST; i += 2) {
+            load9(bufB, invB, (s + 1) / 3, (s + 1) % 3);
+            step(bufA, invA, s / 3, s % 3, i == 0, false);
+            ++s;
+            const bool more = i + 2 < NST;
+            const int sn = more ? s + 1 : s0;
+            load9(bufA, invA, sn / 3, sn % 3, !more && !carry, !more && carry);
+            step(bufB, invB, s / 3, s % 3, false, !more);
+            ++s;
+          }
+          if constexpr (kOddSteps) {
+            load9(bufB, invB, s0 / 3, s0 % 3, !carry, carry);
+            step(bufA, invA, s / 3, s % 3, NST == 1, true);
+          }
+        } else if (s0 < s1) {
           int s = s0;
           load9(bufA, invA, s / 3, s % 3);
           for (;;) {
@@ -634,7 +682,7 @@ __device__ __forceinline__ void counts_block(const uint16_t* __restrict__ counts
         }
       }
     }
-    __syncthreads();
+    lds_barrier();   // the carried prefetch stays in flight across the write-out
 
     for (int i = tid; i < G::NACC; i += THREADS) {
       const uint32_t slot = stream_slot<Q, LB>((uint32_t)i);
@@ -652,7 +700,7 @@ __device__ __forceinline__ void counts_block(const uint16_t* __restrict__ counts
         static_cast<int64_t*>(out)[i] = acc_to_i64(v);
       }
     }
-    __syncthreads();
+    lds_barrier();
   }
 
   if (check_flags) {
