@@ -20,8 +20,10 @@ using lre_detail::record_stage;
 namespace {
 
 constexpr int kMaxQ1 = 7;     // qubits folded by the counts pass
-constexpr int kMaxF = 3;      // qubits folded by a later pass
-constexpr int kMaxFLast = 2;  // qubits folded by the final pass
+constexpr int kMaxF = 3;      // qubits folded by a later pass in registers
+constexpr int kMaxFLast = 2;  // qubits folded by the final pass (below kMinHF4)
+constexpr int kMinHF4 = 5;    // from this many unfolded qubits on, the first later pass
+                              // folds 4 with LDS accumulators and the final one the rest
 constexpr int kRhoJ = 6;      // qubits of the low step-(ii) transform
 constexpr int kRhoRegH = 4;   // high step-(ii) qubits transformed in registers (n <= 10)
 
@@ -70,12 +72,20 @@ bool make_plan(int n, uint64_t shots, uint32_t flags, Plan& P) {
   // Later passes: the last folds at most kMaxFLast qubits (it also divides every
   // output, which costs registers); the others split the rest evenly, <= kMaxF each.
   const int h = n - P.q1;
-  const int last = h < kMaxFLast ? h : kMaxFLast;
-  const int rest = h - last;
-  const int nrest = (rest + kMaxF - 1) / kMaxF;
-  P.npass = nrest + (last > 0 ? 1 : 0);
-  for (int k = 0; k < nrest; ++k) P.F[k] = rest / nrest + (k < rest % nrest ? 1 : 0);
-  if (last > 0) P.F[nrest] = last;
+  if (h >= kMinHF4 && h <= 4 + kMaxF) {
+    // Two passes: 4 qubits (LDS) then the remaining 1..3 in registers, which reads and
+    // writes far less than 3 + 2 + 2 (70 GB instead of 53 GB of partials at n = 14).
+    P.npass = 2;
+    P.F[0] = 4;
+    P.F[1] = h - 4;
+  } else {
+    const int last = h < kMaxFLast ? h : kMaxFLast;
+    const int rest = h - last;
+    const int nrest = (rest + kMaxF - 1) / kMaxF;
+    P.npass = nrest + (last > 0 ? 1 : 0);
+    for (int k = 0; k < nrest; ++k) P.F[k] = rest / nrest + (k < rest % nrest ? 1 : 0);
+    if (last > 0) P.F[nrest] = last;
+  }
   int folded = P.q1;
   Ty prev = P.t1;
   for (int k = 0; k < P.npass; ++k) {
@@ -266,9 +276,20 @@ void launch_foldk(const FoldKArgs& a) {
                      static_cast<const Tin*>(a.in), a.out, a.n, a.h, a.l, a.shots, a.ncols);
 }
 
+template <typename Tin, typename Acc>
+void launch_fold4(const FoldKArgs& a) {
+  const int64_t blocks = (ipow3(a.h - 4) << (a.h - 4)) * (((int64_t)1 << (2 * a.l)) / kF4Cols);
+  hipLaunchKernelGGL((fold_partial4_kernel<Tin, Acc>), dim3((unsigned)blocks), dim3(64 * kF4Waves), 0, a.st,
+                     static_cast<const Tin*>(a.in), static_cast<Acc*>(a.out), a.h, a.l);
+}
+
 template <int F, typename Tin, typename Acc>
 bool foldk_m(Out m, const FoldKArgs& a) {
-  if constexpr (F > kMaxFLast) {  // only the final pass writes coefficients
+  if constexpr (F == 4) {         // LDS pass, partials only
+    if (m != Out::Partial || a.h < 4 || a.l < 3) return false;
+    launch_fold4<Tin, Acc>(a);
+    return true;
+  } else if constexpr (F > kMaxF) {  // only the final pass writes coefficients
     if (m != Out::Partial) return false;
     launch_foldk<F, Tin, Acc, Out::Partial>(a);
     return true;
@@ -296,6 +317,7 @@ bool foldk(int F, Ty tin, Ty tacc, Out m, const FoldKArgs& a) {
     case 1: return foldk_f<1>(tin, tacc, m, a);
     case 2: return foldk_f<2>(tin, tacc, m, a);
     case 3: return foldk_f<3>(tin, tacc, m, a);
+    case 4: return foldk_f<4>(tin, tacc, m, a);
     default: return false;
   }
 }

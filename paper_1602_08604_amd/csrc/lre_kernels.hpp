@@ -24,7 +24,8 @@
 // qubits with an accumulator cascade, applies the lane butterflies to the values that
 // leave the cascade and adds them into a 4^Q LDS accumulator.  Later passes
 // (fold_partial_col / fold_partial_kernel) fold up to 3 more qubits per pass, one
-// thread per column of the fastest-varying a_lo index, entirely in registers.
+// thread per column of the fastest-varying a_lo index, entirely in registers, or 4
+// (fold_partial4_kernel) with the letter codes of 64 columns accumulated in LDS.
 //
 // Step (ii) (Sec. II eq. 4): with x = r XOR c, the entry mu[r][r^x] is a Walsh-Hadamard
 // transform over z in {0,1}^n of e_{a(x,z)} (-i)^{|x&z|}, where per qubit the pair
@@ -967,19 +968,24 @@ __device__ __forceinline__ void fold_partial_col(const Tin* __restrict__ in, voi
   const Tin* __restrict__ p0 = in + b_hi * ipow3(F) * rowstride + (s_hi << F) * L + a_l;
 
   constexpr int NA = (int)ipow4(F);
-  // Final value of folded letter code a (compile-time) for this column.
+  // Final value of folded letter code a (compile-time) for this column.  The divisor
+  // depends on the weight only through the k <= F new non-identity letters: den[k].
   const int wl = MODE == Out::Partial ? 0 : pauli_weight((uint64_t)a_l);
+  double den[F + 1];
+  if constexpr (MODE == Out::CoefUniform || MODE == Out::CoefPerBasis) {
+#pragma unroll
+    for (int k = 0; k <= F; ++k)
+      den[k] = MODE == Out::CoefUniform ? pow3d(n - wl - k) * (double)shots : pow3d(n - wl - k);
+  }
   auto put = [&](auto ac, Acc v) __attribute__((always_inline)) {
     constexpr int a = decltype(ac)::value;
     if constexpr (MODE == Out::Partial) {
       static_cast<Acc*>(out)[bs * (NA * L) + a * L + a_l] = v;
     } else {
       const int64_t i = a * L + a_l;
-      const int w = wl + __builtin_popcount((a | (a >> 1)) & 0x55555555);
-      if constexpr (MODE == Out::CoefUniform)
-        static_cast<double*>(out)[i] = acc_to_double(v) / (pow3d(n - w) * (double)shots);
-      else if constexpr (MODE == Out::CoefPerBasis)
-        static_cast<double*>(out)[i] = acc_to_double(v) / pow3d(n - w);
+      constexpr int k = __builtin_popcount((a | (a >> 1)) & 0x55555555);
+      if constexpr (MODE == Out::CoefUniform || MODE == Out::CoefPerBasis)
+        static_cast<double*>(out)[i] = acc_to_double(v) / den[k];
       else
         static_cast<int64_t*>(out)[i] = acc_to_i64(v);
     }
@@ -1056,6 +1062,73 @@ __global__ __launch_bounds__(256) void fold_partial_kernel(const Tin* __restrict
                                                            int l, uint64_t shots, int64_t ncols) {
   const int64_t col = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (col < ncols) fold_partial_col<F, Tin, Acc, MODE>(in, out, n, h, l, shots, col);
+}
+
+// Later pass folding 4 qubits (partials only): [3^h][2^h][4^l] -> [3^{h-4}][2^{h-4}][4^{4+l}].
+// The 6^4 = 1296 inputs of a column do not fit one thread's registers, so a block takes
+// kF4Cols consecutive columns a_l of one outer index (b_hi, s_hi) and keeps the 4^4
+// letter codes of each column in LDS.  Each of its kF4Waves waves takes 81 / kF4Waves
+// of the basis-digit combinations beta, transforms the 16 outcome values of its column
+// in registers (4-bit Walsh-Hadamard) and adds value m into letter code
+// fold_index(beta, m); the identity letters collect their sums over beta through the
+// LDS atomics.  Loads and stores are coalesced along a_l; the next beta is loaded while
+// the current one is folded.
+constexpr int kF4Cols = 64;
+constexpr int kF4Waves = 9;
+
+template <typename Tin, typename Acc>
+__global__ __launch_bounds__(64 * kF4Waves) void fold_partial4_kernel(const Tin* __restrict__ in,
+                                                                      Acc* __restrict__ out, int h, int l) {
+  constexpr int NS = 16, NA = 256, PER = 81 / kF4Waves, TH = 64 * kF4Waves;
+  static_assert(81 % kF4Waves == 0, "waves must split the 81 digit combinations evenly");
+  __shared__ Acc acc[NA * kF4Cols];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t L = (int64_t)1 << (2 * l);
+  const int64_t groups = L / kF4Cols;
+  const int64_t bs = blockIdx.x / groups;
+  const int64_t c0 = (blockIdx.x % groups) * kF4Cols;
+  const int hr = h - 4;
+  const int64_t s_hi = bs & (((int64_t)1 << hr) - 1);
+  const int64_t b_hi = bs >> hr;
+  const int64_t rowstride = ((int64_t)1 << h) * L;
+  const Tin* __restrict__ p0 = in + b_hi * 81 * rowstride + (s_hi << 4) * L + c0 + lane;
+
+  for (int i = tid; i < NA * kF4Cols; i += TH) acc[i] = Acc(0);
+  __syncthreads();
+
+  auto load = [&](int beta, Acc (&x)[NS]) __attribute__((always_inline)) {
+    const Tin* __restrict__ p = p0 + beta * rowstride;
+#pragma unroll
+    for (int sg = 0; sg < NS; ++sg) x[sg] = in_to_acc<Tin, Acc>(p[sg * L]);
+  };
+  auto fold = [&](int beta, Acc (&x)[NS]) __attribute__((always_inline)) {
+    wht_regs<4>(x);
+    const uint32_t t0 = (uint32_t)(beta % 3 + 1), t1 = (uint32_t)((beta / 3) % 3 + 1) << 2;
+    const uint32_t t2 = (uint32_t)((beta / 9) % 3 + 1) << 4, t3 = (uint32_t)(beta / 27 + 1) << 6;
+#pragma unroll
+    for (int m = 0; m < NS; ++m) {
+      const uint32_t a = ((m & 1) ? t0 : 0u) | ((m & 2) ? t1 : 0u) | ((m & 4) ? t2 : 0u) | ((m & 8) ? t3 : 0u);
+      atomicAdd(&acc[a * kF4Cols + lane], x[m]);
+    }
+  };
+  Acc xa[NS], xb[NS];
+  int beta = wave;   // this wave's digit combinations: wave, wave + kF4Waves, ...
+  load(beta, xa);
+#pragma unroll 1
+  for (int j = 0; j < PER; j += 2) {
+    if (j + 1 < PER) load(beta + kF4Waves, xb);
+    fold(beta, xa);
+    if (j + 1 >= PER) break;
+    beta += kF4Waves;
+    if (j + 2 < PER) load(beta + kF4Waves, xa);
+    fold(beta, xb);
+    beta += kF4Waves;
+  }
+  __syncthreads();
+
+  Acc* __restrict__ o = out + bs * NA * L + c0;
+  for (int i = tid; i < NA * kF4Cols; i += TH) o[(int64_t)(i / kF4Cols) * L + (i % kF4Cols)] = acc[i];
 }
 
 // ---------------------------------------------------------------------------------
