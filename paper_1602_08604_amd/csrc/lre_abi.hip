@@ -278,7 +278,16 @@ void launch_foldk(const FoldKArgs& a) {
 
 template <typename Tin, typename Acc>
 void launch_fold4(const FoldKArgs& a) {
-  const int64_t blocks = (ipow3(a.h - 4) << (a.h - 4)) * (((int64_t)1 << (2 * a.l)) / kF4Cols);
+  // Persistent blocks: as many as the device holds at once (LDS-bound), each walking
+  // groups with a stride of the grid.
+  const int64_t groups = (ipow3(a.h - 4) << (a.h - 4)) * (((int64_t)1 << (2 * a.l)) / kF4Cols);
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+    cus = 256;
+  const int64_t per_cu = (160 * 1024) / ((int64_t)256 * kF4Cols * (int64_t)sizeof(Acc));
+  const int64_t cap = (int64_t)cus * (per_cu > 0 ? per_cu : 1);
+  const int64_t blocks = groups < cap ? groups : cap;
   hipLaunchKernelGGL((fold_partial4_kernel<Tin, Acc>), dim3((unsigned)blocks), dim3(64 * kF4Waves), 0, a.st,
                      static_cast<const Tin*>(a.in), static_cast<Acc*>(a.out), a.h, a.l);
 }

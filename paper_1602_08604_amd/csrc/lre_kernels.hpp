@@ -1065,14 +1065,17 @@ __global__ __launch_bounds__(256) void fold_partial_kernel(const Tin* __restrict
 }
 
 // Later pass folding 4 qubits (partials only): [3^h][2^h][4^l] -> [3^{h-4}][2^{h-4}][4^{4+l}].
-// The 6^4 = 1296 inputs of a column do not fit one thread's registers, so a block takes
-// kF4Cols consecutive columns a_l of one outer index (b_hi, s_hi) and keeps the 4^4
-// letter codes of each column in LDS.  Each of its kF4Waves waves takes 81 / kF4Waves
+// The 6^4 = 1296 inputs of a column do not fit one thread's registers, so a group of
+// kF4Cols consecutive columns a_l of one outer index (b_hi, s_hi) keeps the 4^4 letter
+// codes of each column in LDS.  Each of the block's kF4Waves waves takes 81 / kF4Waves
 // of the basis-digit combinations beta, transforms the 16 outcome values of its column
 // in registers (4-bit Walsh-Hadamard) and adds value m into letter code
 // fold_index(beta, m); the identity letters collect their sums over beta through the
-// LDS atomics.  Loads and stores are coalesced along a_l; the next beta is loaded while
-// the current one is folded.
+// LDS atomics.  Loads and stores are coalesced along a_l.  Blocks are persistent (one
+// per LDS-sized slot of the device) and walk groups g, g + gridDim.x, ...: the next
+// beta is loaded while the current one is folded, and a wave's last load of a group
+// fetches its first beta of the next group, which stays in flight across the
+// write-out (LDS-only barriers).
 constexpr int kF4Cols = 64;
 constexpr int kF4Waves = 9;
 
@@ -1080,27 +1083,28 @@ template <typename Tin, typename Acc>
 __global__ __launch_bounds__(64 * kF4Waves) void fold_partial4_kernel(const Tin* __restrict__ in,
                                                                       Acc* __restrict__ out, int h, int l) {
   constexpr int NS = 16, NA = 256, PER = 81 / kF4Waves, TH = 64 * kF4Waves;
-  static_assert(81 % kF4Waves == 0, "waves must split the 81 digit combinations evenly");
+  static_assert(81 % kF4Waves == 0 && PER % 2 == 1, "waves split the 81 combinations into odd counts");
   __shared__ Acc acc[NA * kF4Cols];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t L = (int64_t)1 << (2 * l);
-  const int64_t groups = L / kF4Cols;
-  const int64_t bs = blockIdx.x / groups;
-  const int64_t c0 = (blockIdx.x % groups) * kF4Cols;
+  const int64_t per_outer = L / kF4Cols;
   const int hr = h - 4;
-  const int64_t s_hi = bs & (((int64_t)1 << hr) - 1);
-  const int64_t b_hi = bs >> hr;
+  const int64_t total = (ipow3(hr) << hr) * per_outer;
   const int64_t rowstride = ((int64_t)1 << h) * L;
-  const Tin* __restrict__ p0 = in + b_hi * 81 * rowstride + (s_hi << 4) * L + c0 + lane;
-
-  for (int i = tid; i < NA * kF4Cols; i += TH) acc[i] = Acc(0);
-  __syncthreads();
-
-  auto load = [&](int beta, Acc (&x)[NS]) __attribute__((always_inline)) {
+  // First input of group g for this lane; the group's outer index and first column.
+  auto group_in = [&](int64_t g) __attribute__((always_inline)) {
+    const int64_t bs = g / per_outer, c0 = (g % per_outer) * kF4Cols;
+    const int64_t s_hi = bs & (((int64_t)1 << hr) - 1), b_hi = bs >> hr;
+    return in + b_hi * 81 * rowstride + (s_hi << 4) * L + c0 + lane;
+  };
+  // The loads are issued where they stand (the scheduler would otherwise sink them
+  // below the transform of the previous buffer and the prefetch would not overlap it).
+  auto load = [&](const Tin* __restrict__ p0, int beta, Acc (&x)[NS]) __attribute__((always_inline)) {
     const Tin* __restrict__ p = p0 + beta * rowstride;
 #pragma unroll
     for (int sg = 0; sg < NS; ++sg) x[sg] = in_to_acc<Tin, Acc>(p[sg * L]);
+    __builtin_amdgcn_sched_barrier(0);
   };
   auto fold = [&](int beta, Acc (&x)[NS]) __attribute__((always_inline)) {
     wht_regs<4>(x);
@@ -1112,23 +1116,44 @@ __global__ __launch_bounds__(64 * kF4Waves) void fold_partial4_kernel(const Tin*
       atomicAdd(&acc[a * kF4Cols + lane], x[m]);
     }
   };
-  Acc xa[NS], xb[NS];
-  int beta = wave;   // this wave's digit combinations: wave, wave + kF4Waves, ...
-  load(beta, xa);
-#pragma unroll 1
-  for (int j = 0; j < PER; j += 2) {
-    if (j + 1 < PER) load(beta + kF4Waves, xb);
-    fold(beta, xa);
-    if (j + 1 >= PER) break;
-    beta += kF4Waves;
-    if (j + 2 < PER) load(beta + kF4Waves, xa);
-    fold(beta, xb);
-    beta += kF4Waves;
-  }
-  __syncthreads();
 
-  Acc* __restrict__ o = out + bs * NA * L + c0;
-  for (int i = tid; i < NA * kF4Cols; i += TH) o[(int64_t)(i / kF4Cols) * L + (i % kF4Cols)] = acc[i];
+  for (int i = tid; i < NA * kF4Cols; i += TH) acc[i] = Acc(0);
+  __syncthreads();
+  int64_t g = blockIdx.x;
+  if (g >= total) return;
+  Acc xa[NS], xb[NS];
+  const Tin* __restrict__ p = group_in(g);
+  load(p, wave, xa);
+  for (;;) {
+    const int64_t gn = g + gridDim.x;
+    const bool carry = gn < total;
+    const Tin* __restrict__ pn = carry ? group_in(gn) : p;   // else a cached reload
+    int beta = wave;   // this wave's combinations: wave, wave + kF4Waves, ...
+    for (int j = 0; j + 1 < PER; j += 2) {
+      load(p, beta + kF4Waves, xb);
+      fold(beta, xa);
+      beta += kF4Waves;
+      load(p, beta + kF4Waves, xa);
+      fold(beta, xb);
+      beta += kF4Waves;
+    }
+    load(pn, wave, xb);
+    fold(beta, xa);
+    lds_barrier();
+
+    const int64_t bs = g / per_outer, c0 = (g % per_outer) * kF4Cols;
+    Acc* __restrict__ o = out + bs * NA * L + c0;
+    for (int i = tid; i < NA * kF4Cols; i += TH) {
+      const Acc v = acc[i];
+      acc[i] = Acc(0);
+      o[(int64_t)(i / kF4Cols) * L + (i % kF4Cols)] = v;
+    }
+    lds_barrier();
+    if (!carry) break;
+    g = gn;
+    p = pn;
+    StaticFor<0, NS>::run([&](auto kc) __attribute__((always_inline)) { xa[decltype(kc)::value] = xb[decltype(kc)::value]; });
+  }
 }
 
 // ---------------------------------------------------------------------------------
