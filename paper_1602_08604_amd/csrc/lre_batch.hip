@@ -165,20 +165,43 @@ __device__ __noinline__ void run_counts(const BInstG& I, int64_t g0, int64_t g1,
   }
 }
 
+// Final fold of F = n - 7 qubits over columns [c0, c1): every thread first gathers the
+// 6^F inputs of C columns into registers, then folds them.  (Folding straight from
+// memory serialises the columns: the next column's loads cannot pass this column's
+// coefficient stores, and the loads' wait covers the stores.)
+template <int F>
+__device__ __forceinline__ void fold_cols(const uint32_t* in, double* coef, int n, uint64_t shots, int64_t c0,
+                                          int64_t c1, int tid) {
+  constexpr int NIN = (int)ipow3(F) << F, C = 4;
+  for (int64_t base = c0 + tid; base < c1; base += (int64_t)kBT * C) {
+    uint32_t x[C][NIN];
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const int64_t col = base + (int64_t)j * kBT;
+      if (col < c1) {
+#pragma unroll
+        for (int beta = 0; beta < (int)ipow3(F); ++beta)
+#pragma unroll
+          for (int sg = 0; sg < (1 << F); ++sg) x[j][beta * (1 << F) + sg] = in[fold_in_offset<F>(F, kQ, col, beta, sg)];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+      const int64_t col = base + (int64_t)j * kBT;
+      if (col < c1)
+        fold_partial_col_src<F, uint32_t, uint32_t, Out::CoefUniform>(
+            [&](int beta, int sg) __attribute__((always_inline)) { return x[j][beta * (1 << F) + sg]; }, coef,
+            n, F, kQ, shots, col);
+    }
+  }
+}
+
 __device__ __noinline__ void run_fold(const BInstG& I, int64_t c0, int64_t c1, int tid, LRE_GLOBAL char* ws) {
   const uint32_t* in = reinterpret_cast<const uint32_t*>(g2p(ws + I.off_part));
   double* coef = (double*)I.coef;
   const int h = I.n - kQ;
-  // four columns per thread at a time, so that their loads are in flight together
-  if (h == 1) {
-#pragma unroll 4
-    for (int64_t col = c0 + tid; col < c1; col += kBT)
-      fold_partial_col<1, uint32_t, uint32_t, Out::CoefUniform>(in, coef, I.n, h, kQ, I.shots, col);
-  } else {
-#pragma unroll 4
-    for (int64_t col = c0 + tid; col < c1; col += kBT)
-      fold_partial_col<2, uint32_t, uint32_t, Out::CoefUniform>(in, coef, I.n, h, kQ, I.shots, col);
-  }
+  if (h == 1) fold_cols<1>(in, coef, I.n, I.shots, c0, c1, tid);
+  else fold_cols<2>(in, coef, I.n, I.shots, c0, c1, tid);
 }
 
 // Step (ii) for the x_hi values [x0, x1) of an instance with n > 7: the low transform of

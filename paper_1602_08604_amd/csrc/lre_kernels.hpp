@@ -953,11 +953,10 @@ __device__ __forceinline__ Acc in_to_acc(Tin v) {
   else return (Acc)v;
 }
 
-// One column of a later pass: folds F more qubits of the partial tensor for the
-// fastest-varying index column `col` (one thread per column, all in registers).
-template <int F, typename Tin, typename Acc, Out MODE>
-__device__ __forceinline__ void fold_partial_col(const Tin* __restrict__ in, void* __restrict__ out, int n,
-                                                 int h, int l, uint64_t shots, int64_t col) {
+// Input element (beta, sg) of column `col` in a later pass: beta = basis digits and
+// sg = outcome bits of the F qubits being folded.
+template <int F>
+__device__ __forceinline__ int64_t fold_in_offset(int h, int l, int64_t col, int beta, int sg) {
   const int64_t L = (int64_t)1 << (2 * l);
   const int64_t a_l = col & (L - 1);
   const int64_t bs = col >> (2 * l);
@@ -965,7 +964,18 @@ __device__ __forceinline__ void fold_partial_col(const Tin* __restrict__ in, voi
   const int64_t s_hi = bs & (((int64_t)1 << hr) - 1);
   const int64_t b_hi = bs >> hr;
   const int64_t rowstride = ((int64_t)1 << h) * L;
-  const Tin* __restrict__ p0 = in + b_hi * ipow3(F) * rowstride + (s_hi << F) * L + a_l;
+  return (b_hi * ipow3(F) + beta) * rowstride + ((s_hi << F) + sg) * L + a_l;
+}
+
+// One column of a later pass: folds F more qubits of the partial tensor for the
+// fastest-varying index column `col` (one thread per column, all in registers).
+// src(beta, sg) returns input element (beta, sg) of the column as Tin.
+template <int F, typename Tin, typename Acc, Out MODE, class Src>
+__device__ __forceinline__ void fold_partial_col_src(Src&& src, void* __restrict__ out, int n, int h, int l,
+                                                     uint64_t shots, int64_t col) {
+  const int64_t L = (int64_t)1 << (2 * l);
+  const int64_t a_l = col & (L - 1);
+  const int64_t bs = col >> (2 * l);
 
   constexpr int NA = (int)ipow4(F);
   // Final value of folded letter code a (compile-time) for this column.  The divisor
@@ -992,7 +1002,7 @@ __device__ __forceinline__ void fold_partial_col(const Tin* __restrict__ in, voi
   };
   auto load_row = [&](int beta, Acc* x) __attribute__((always_inline)) {
 #pragma unroll
-    for (int sg = 0; sg < (1 << F); ++sg) x[sg] = in_to_acc<Tin, Acc>(p0[beta * rowstride + sg * L]);
+    for (int sg = 0; sg < (1 << F); ++sg) x[sg] = in_to_acc<Tin, Acc>(src(beta, sg));
     wht_regs<F>(x);
   };
   using I0 = std::integral_constant<int, 0>;
@@ -1054,6 +1064,17 @@ __device__ __forceinline__ void fold_partial_col(const Tin* __restrict__ in, voi
     StaticFor<0, NA>::run([&](auto ac) __attribute__((always_inline)) { put(ac, acc[decltype(ac)::value]); });
   }
   (void)sizeof(I0);
+}
+
+template <int F, typename Tin, typename Acc, Out MODE>
+__device__ __forceinline__ void fold_partial_col(const Tin* __restrict__ in, void* __restrict__ out, int n,
+                                                 int h, int l, uint64_t shots, int64_t col) {
+  const int64_t L = (int64_t)1 << (2 * l);
+  const int64_t rowstride = ((int64_t)1 << h) * L;
+  const Tin* __restrict__ p0 = in + fold_in_offset<F>(h, l, col, 0, 0);
+  fold_partial_col_src<F, Tin, Acc, MODE>(
+      [&](int beta, int sg) __attribute__((always_inline)) { return p0[beta * rowstride + sg * L]; }, out, n, h,
+      l, shots, col);
 }
 
 template <int F, typename Tin, typename Acc, Out MODE>
