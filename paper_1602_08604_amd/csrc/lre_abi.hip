@@ -127,6 +127,21 @@ bool make_plan(int n, uint64_t shots, uint32_t flags, Plan& P) {
   return true;
 }
 
+// Blocks of `kernel` the device holds at once (compute units x resident blocks per
+// unit); a persistent grid of this size has no second wave of blocks.
+// lds_bytes: the kernel's static LDS, which bounds the count to 160 KiB per unit.
+template <class K>
+int64_t resident_blocks(K kernel, int threads, int64_t lds_bytes) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+    cus = 256;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu <= 0)
+    per_cu = 1;
+  const int64_t by_lds = std::max<int64_t>(1, (160 * 1024) / std::max<int64_t>(1, lds_bytes));
+  return (int64_t)cus * std::min<int64_t>(per_cu, by_lds);
+}
+
 // ---- launch helpers -------------------------------------------------------------
 
 struct Fold1Args {
@@ -278,15 +293,11 @@ void launch_foldk(const FoldKArgs& a) {
 
 template <typename Tin, typename Acc>
 void launch_fold4(const FoldKArgs& a) {
-  // Persistent blocks: as many as the device holds at once (LDS-bound), each walking
+  // Persistent blocks: as many as the device holds at once, each walking
   // groups with a stride of the grid.
   const int64_t groups = (ipow3(a.h - 4) << (a.h - 4)) * (((int64_t)1 << (2 * a.l)) / kF4Cols);
-  int dev = 0, cus = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-    cus = 256;
-  const int64_t per_cu = (160 * 1024) / ((int64_t)256 * kF4Cols * (int64_t)sizeof(Acc));
-  const int64_t cap = (int64_t)cus * (per_cu > 0 ? per_cu : 1);
+  const int64_t cap = resident_blocks(fold_partial4_kernel<Tin, Acc>, 64 * kF4Waves,
+                                      (int64_t)256 * kF4Cols * (int64_t)sizeof(Acc));
   const int64_t blocks = groups < cap ? groups : cap;
   hipLaunchKernelGGL((fold_partial4_kernel<Tin, Acc>), dim3((unsigned)blocks), dim3(64 * kF4Waves), 0, a.st,
                      static_cast<const Tin*>(a.in), static_cast<Acc*>(a.out), a.h, a.l);
@@ -331,6 +342,16 @@ bool foldk(int F, Ty tin, Ty tacc, Out m, const FoldKArgs& a) {
   }
 }
 
+// Persistent high transform: as many blocks as the LDS lets the device hold.
+template <int H, typename OutT>
+void launch_rho_high2(const double2* tmp, void* rho, int n, hipStream_t st) {
+  using G = RhoHigh2Geom<H>;
+  const int64_t items = ((int64_t)1 << H) * G::D * (G::D / G::XB);
+  const int64_t blocks =
+      std::min<int64_t>(items, resident_blocks(rho_high2_kernel<H, OutT>, 256, 2LL * G::NH * G::SP * 8));
+  hipLaunchKernelGGL((rho_high2_kernel<H, OutT>), dim3((unsigned)blocks), dim3(256), 0, st, tmp, rho, n, items);
+}
+
 template <typename OutT>
 void launch_rho(const Plan& P, const double* coef, void* rho, char* ws, hipStream_t st) {
   const int n = P.n;
@@ -359,14 +380,11 @@ void launch_rho(const Plan& P, const double* coef, void* rho, char* ws, hipStrea
     return;
   }
   // 5..8 high qubits: two register phases with one LDS transpose
-  const int H = n - kRhoJ;
-  const int64_t xb = std::min<int64_t>(D, 4096 >> H);
-  const dim3 grid((unsigned)(((int64_t)1 << H) * D * (D / xb)));
-  switch (H) {
-    case 5: hipLaunchKernelGGL((rho_high2_kernel<5, OutT>), grid, dim3(256), 0, st, (const double2*)tmp, rho, n); break;
-    case 6: hipLaunchKernelGGL((rho_high2_kernel<6, OutT>), grid, dim3(256), 0, st, (const double2*)tmp, rho, n); break;
-    case 7: hipLaunchKernelGGL((rho_high2_kernel<7, OutT>), grid, dim3(256), 0, st, (const double2*)tmp, rho, n); break;
-    default: hipLaunchKernelGGL((rho_high2_kernel<8, OutT>), grid, dim3(256), 0, st, (const double2*)tmp, rho, n); break;
+  switch (n - kRhoJ) {
+    case 5: launch_rho_high2<5, OutT>(tmp, rho, n, st); break;
+    case 6: launch_rho_high2<6, OutT>(tmp, rho, n, st); break;
+    case 7: launch_rho_high2<7, OutT>(tmp, rho, n, st); break;
+    default: launch_rho_high2<8, OutT>(tmp, rho, n, st); break;
   }
 }
 

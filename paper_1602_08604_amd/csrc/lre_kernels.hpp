@@ -1507,68 +1507,106 @@ static __global__ __launch_bounds__(256) void rho_low6_kernel(const double* __re
 // block of XB consecutive x_lo).  z = zA + 16 zB: phase A transforms zA (4 bits) in
 // registers per (x_lo, zB) and stores to LDS; phase B transforms zB (H - 4 bits) in
 // registers per (x_lo, zA) and writes rows r_hi = zA' + 16 zB' of mu.
+template <int H>
+struct RhoHigh2Geom {
+  static constexpr int D = 64, NH = 1 << H, HB = H - 4, NB = 1 << HB;
+  static constexpr int XB = (4096 / NH) < D ? (4096 / NH) : D;  // x_lo values per item
+  static constexpr int SP = XB + 1;                              // padded LDS row (one z)
+};
+
+// Blocks are persistent (as many as the device holds at once) and walk items
+// (x_hi, r_lo, x_lo block) with a stride of the grid; a block loads its next item's
+// inputs while it transposes and stores the current one.
 template <int H, typename OutT>
 __global__ __launch_bounds__(256) void rho_high2_kernel(const double2* __restrict__ tmp, void* __restrict__ rho,
-                                                        int n) {
-  constexpr int J = 6, D = 64, NH = 1 << H, HB = H - 4, NB = 1 << HB;
-  constexpr int XB = (4096 / NH) < D ? (4096 / NH) : D;
-  constexpr int SP = XB + 1;  // padded LDS row (one z) stride
-  __shared__ double sre[NH * SP], sim[NH * SP];
-  int64_t bid = blockIdx.x;
-  const int xblk = (int)(bid % (D / XB));
-  bid /= (D / XB);
-  const int r_lo = (int)(bid % D);
-  const int x_hi = (int)(bid / D);
+                                                        int n, int64_t items) {
+  using G = RhoHigh2Geom<H>;
+  constexpr int J = 6, D = G::D, NB = G::NB, HB = G::HB, XB = G::XB, SP = G::SP;
+  static_assert(XB * NB <= 256, "phase A takes at most one item per thread");
+  __shared__ double sre[G::NH * SP], sim[G::NH * SP];
   const int t = threadIdx.x;
-  // phase A: items (xo, zB), xo fastest
-  for (int it = t; it < XB * NB; it += 256) {
-    const int xo = it % XB, zB = it / XB;
-    const int x_lo = xblk * XB + xo;
-    double re[16], im[16];
+  const bool has_a = t < XB * NB;
+  const int xo_a = t % XB, zB_a = t / XB;
+  struct Item { int xblk, r_lo, x_hi; };
+  auto decode = [&](int64_t it) __attribute__((always_inline)) {
+    Item w;
+    w.xblk = (int)(it % (D / XB));
+    it /= (D / XB);
+    w.r_lo = (int)(it % D);
+    w.x_hi = (int)(it / D);
+    return w;
+  };
+  // Phase A inputs of item w for this thread: 16 values z = zA + 16 zB_a.
+  auto load_a = [&](const Item& w, double (&re)[16], double (&im)[16]) __attribute__((always_inline)) {
+    const int x_lo = w.xblk * XB + xo_a;
 #pragma unroll
     for (int zA = 0; zA < 16; ++zA) {
-      const int z = zA + 16 * zB;
+      const int z = zA + 16 * zB_a;
       int64_t a_hi = 0;
 #pragma unroll
       for (int p = H - 1; p >= 0; --p) {
-        const int xb = (x_hi >> p) & 1, zb = (z >> p) & 1;
+        const int xb = (w.x_hi >> p) & 1, zb = (z >> p) & 1;
         a_hi = a_hi * 4 + (xb ? (zb ? 2 : 1) : (zb ? 3 : 0));
       }
-      const double2 v = tmp[(a_hi * D + r_lo) * D + x_lo];
+      const double2 v = tmp[(a_hi * D + w.r_lo) * D + x_lo];
       re[zA] = v.x;
       im[zA] = v.y;
-      mul_neg_i_pow(__popc((unsigned)(x_hi & z)), re[zA], im[zA]);
     }
-    wht_regs<4>(re);
-    wht_regs<4>(im);
-#pragma unroll
-    for (int zA = 0; zA < 16; ++zA) {
-      sre[(zA + 16 * zB) * SP + xo] = re[zA];
-      sim[(zA + 16 * zB) * SP + xo] = im[zA];
-    }
-  }
-  __syncthreads();
+    __builtin_amdgcn_sched_barrier(0);   // issue the loads here, ahead of the current item's work
+  };
   const double scale = ldexp(1.0, -n);
   const int64_t dn = (int64_t)1 << n;
-  // phase B: items (xo, zA), xo fastest
-  for (int it = t; it < XB * 16; it += 256) {
-    const int xo = it % XB, zA = it / XB;
-    const int x_lo = xblk * XB + xo;
-    double re[NB], im[NB];
+
+  int64_t it = blockIdx.x;
+  if (it >= items) return;
+  Item w = decode(it);
+  double nre[16], nim[16];
+  if (has_a) load_a(w, nre, nim);
+  for (;;) {
+    if (has_a) {
+      double re[16], im[16];
 #pragma unroll
-    for (int zB = 0; zB < NB; ++zB) {
-      re[zB] = sre[(zA + 16 * zB) * SP + xo];
-      im[zB] = sim[(zA + 16 * zB) * SP + xo];
-    }
-    wht_regs<HB>(re);
-    wht_regs<HB>(im);
+      for (int zA = 0; zA < 16; ++zA) {
+        re[zA] = nre[zA];
+        im[zA] = nim[zA];
+        mul_neg_i_pow(__popc((unsigned)(w.x_hi & (zA + 16 * zB_a))), re[zA], im[zA]);
+      }
+      wht_regs<4>(re);
+      wht_regs<4>(im);
 #pragma unroll
-    for (int zB = 0; zB < NB; ++zB) {
-      const int r_hi = zA + 16 * zB;
-      const int64_t row = ((int64_t)r_hi << J) | r_lo;
-      const int64_t col = ((int64_t)(r_hi ^ x_hi) << J) | (r_lo ^ x_lo);
-      store_complex<OutT>(rho, row * dn + col, re[zB] * scale, im[zB] * scale);
+      for (int zA = 0; zA < 16; ++zA) {
+        sre[(zA + 16 * zB_a) * SP + xo_a] = re[zA];
+        sim[(zA + 16 * zB_a) * SP + xo_a] = im[zA];
+      }
     }
+    lds_barrier();
+    const int64_t nx = it + gridDim.x;
+    const Item wn = decode(nx < items ? nx : it);
+    if (has_a && nx < items) load_a(wn, nre, nim);
+    // phase B: items (xo, zA), xo fastest
+    for (int ib = t; ib < XB * 16; ib += 256) {
+      const int xo = ib % XB, zA = ib / XB;
+      const int x_lo = w.xblk * XB + xo;
+      double re[NB], im[NB];
+#pragma unroll
+      for (int zB = 0; zB < NB; ++zB) {
+        re[zB] = sre[(zA + 16 * zB) * SP + xo];
+        im[zB] = sim[(zA + 16 * zB) * SP + xo];
+      }
+      wht_regs<HB>(re);
+      wht_regs<HB>(im);
+#pragma unroll
+      for (int zB = 0; zB < NB; ++zB) {
+        const int r_hi = zA + 16 * zB;
+        const int64_t row = ((int64_t)r_hi << J) | w.r_lo;
+        const int64_t col = ((int64_t)(r_hi ^ w.x_hi) << J) | (w.r_lo ^ x_lo);
+        store_complex<OutT>(rho, row * dn + col, re[zB] * scale, im[zB] * scale);
+      }
+    }
+    lds_barrier();
+    if (nx >= items) break;
+    it = nx;
+    w = wn;
   }
 }
 
