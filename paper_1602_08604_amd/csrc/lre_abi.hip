@@ -365,7 +365,9 @@ void launch_rho(const Plan& P, const double* coef, void* rho, char* ws, hipStrea
     return;
   }
   double2* tmp = reinterpret_cast<double2*>(ws + P.off_tmp);
-  hipLaunchKernelGGL(rho_low6_kernel, dim3((unsigned)ipow4(n - kRhoJ)), dim3(256), 0, st, coef, tmp);
+  const int64_t nblk = ipow4(n - kRhoJ);
+  const int64_t low_blocks = std::min<int64_t>(nblk, resident_blocks(rho_low6_kernel, 256, 4096 * 8));
+  hipLaunchKernelGGL(rho_low6_kernel, dim3((unsigned)low_blocks), dim3(256), 0, st, coef, tmp, nblk);
   const int64_t D = (int64_t)1 << kRhoJ;
   if (n - kRhoJ <= kRhoRegH) {
     // few high qubits: one thread per (x_hi, r_lo, x_lo), transform in registers

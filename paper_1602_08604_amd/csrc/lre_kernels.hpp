@@ -1456,18 +1456,6 @@ __device__ __forceinline__ void rho_low6_from_lds(const double* __restrict__ blk
   for (int k = 0; k < 16; ++k) o[(zl + 4u * (uint32_t)k) * 64u + x] = make_double2(re[k], im[k]);
 }
 
-// blk: LDS of 4096 doubles.  Every thread of the block calls this (it synchronises);
-// threads 0..255 do the transform, the caller synchronises before reusing blk.
-template <int THREADS>
-__device__ __forceinline__ void rho_low6_block(const double* __restrict__ coef, double2* __restrict__ tmp,
-                                               int64_t a_hi, int t, double* __restrict__ blk) {
-  static_assert(THREADS >= 256, "one thread per (x, z quad)");
-  const double* __restrict__ e = coef + a_hi * 4096;
-  for (int i = t; i < 4096; i += THREADS) blk[i] = e[i];
-  __syncthreads();
-  if (t < 256) rho_low6_from_lds(blk, tmp, a_hi, t);
-}
-
 // nz blocks a_hi = a_of(0 .. nz-1) in sequence, the next block's coefficients loaded into
 // registers while the current one is transformed.
 template <int THREADS, typename AOf>
@@ -1483,11 +1471,11 @@ __device__ __forceinline__ void rho_low6_blocks(const double* __restrict__ coef,
       if (t + THREADS * i < 4096) pre[i] = e[t + THREADS * i];
   }
   for (int z = 0; z < nz; ++z) {
-    __syncthreads();  // the previous block's transform has read blk
+    lds_barrier();  // the previous block's transform has read blk
 #pragma unroll
     for (int i = 0; i < PER; ++i)
       if (t + THREADS * i < 4096) blk[t + THREADS * i] = pre[i];
-    __syncthreads();
+    lds_barrier();
     if (z + 1 < nz) {
       const double* __restrict__ e = coef + a_of(z + 1) * 4096;
 #pragma unroll
@@ -1498,9 +1486,15 @@ __device__ __forceinline__ void rho_low6_blocks(const double* __restrict__ coef,
   }
 }
 
-static __global__ __launch_bounds__(256) void rho_low6_kernel(const double* __restrict__ coef, double2* __restrict__ tmp) {
+// Persistent: block b transforms coefficient blocks b, b + gridDim.x, ... < nblk, each
+// block's coefficients loaded while the previous one is transformed.
+static __global__ __launch_bounds__(256) void rho_low6_kernel(const double* __restrict__ coef, double2* __restrict__ tmp,
+                                                              int64_t nblk) {
   __shared__ double blk[4096];
-  rho_low6_block<256>(coef, tmp, blockIdx.x, threadIdx.x, blk);
+  const int64_t b0 = blockIdx.x, st = gridDim.x;
+  if (b0 >= nblk) return;
+  const int nz = (int)((nblk - 1 - b0) / st + 1);
+  rho_low6_blocks<256>(coef, tmp, [&](int z) { return b0 + (int64_t)z * st; }, nz, threadIdx.x, blk);
 }
 
 // High transform for H = n - 6 in [5, 8] high qubits, 256 threads.  Block -> (x_hi, r_lo,
