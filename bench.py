@@ -113,6 +113,35 @@ def make_workload(name, torch):
     raise SystemExit(f"unknown workload {name}")
 
 
+def measured_hbm(torch, lre, gib=8, reps=5):
+    """Practical HBM rates of this device next to the 8 TB/s datasheet peak: the library's
+    streaming read (lre_stream_read) and copy (lre_stream_copy, read + write) over `gib`
+    GiB, timed with events on the current stream after one warm-up each."""
+    n = gib << 28
+    x = torch.ones(n, dtype=torch.int32, device="cuda:0")
+    y = torch.empty_like(x)
+    sink = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+    nbytes = 4.0 * n
+
+    def rate(fn, moved):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return moved * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+
+    read = rate(lambda: lre.stream_read(x, sink), nbytes)
+    copy = rate(lambda: lre.stream_copy(x, y), 2.0 * nbytes)
+    del x, y, sink
+    torch.cuda.empty_cache()
+    return {"stream_read_gbs": read, "stream_copy_gbs": copy, "unit": "GB/s", "bytes_each": nbytes,
+            "how": f"lre_stream_read / lre_stream_copy (16-byte vectors, a contiguous range per block) over {gib} GiB, "
+                   f"{reps} reps each; copy counts read + write bytes"}
+
+
 def host_cpu():
     """Model name and logical CPU count of the host the oracle runs on."""
     model = "unknown"
@@ -425,6 +454,8 @@ def main():
             "signed_sums": "bit-identical (tests/test_gpu_parity.py)"}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload, n, shots, counts, coef)
+    if not args.no_compare:
+        out["hbm_measured"] = measured_hbm(torch, lre)
     print(json.dumps(out), flush=True)
 
 

@@ -209,6 +209,18 @@ lre_status lre_batch_run(lre_batch* plan, void* workspace, size_t workspace_byte
 /* Free the plan and its work list (NULL is ignored). */
 void lre_batch_destroy(lre_batch* plan);
 
+/* ---------------------------------------------------------------------------------
+ * Device streaming rates (diagnostics, not part of the method): plain kernels with
+ * 16-byte vector accesses (each block a contiguous range), used to state the practical
+ * HBM ceiling next to the datasheet peak.  Enqueued on `stream`; time them with events around the call.
+ *   lre_stream_read : reads `bytes` at `buf`; `sink` is a device uint32 that may be
+ *                     written (it keeps the loads from being optimised away).
+ *   lre_stream_copy : copies `bytes` from `src` to `dst` (non-overlapping).
+ * Pointers are device pointers, 16-byte aligned; `bytes` is a multiple of 16, else
+ * LRE_E_ARG.  The caller owns every buffer. */
+lre_status lre_stream_read(const void* buf, size_t bytes, uint32_t* sink, void* stream);
+lre_status lre_stream_copy(const void* src, void* dst, size_t bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

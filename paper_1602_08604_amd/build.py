@@ -13,7 +13,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB_DIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(LIB_DIR, "liblre.so")
-SOURCES = [os.path.join(PKG, "csrc", "lre_abi.hip"), os.path.join(PKG, "csrc", "lre_batch.hip")]
+SOURCES = [os.path.join(PKG, "csrc", f) for f in ("lre_abi.hip", "lre_batch.hip", "lre_membench.hip")]
 DEPS = SOURCES + [os.path.join(PKG, "csrc", f) for f in ("lre_kernels.hpp", "lre_internal.hpp")] + [
     os.path.join(ROOT, "include", "lre.h")]
 

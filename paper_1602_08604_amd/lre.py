@@ -93,6 +93,10 @@ def lib():
         L.lre_batch_tune.restype = I
         L.lre_batch_run.argtypes = [P, P, SZ, P]
         L.lre_batch_run.restype = I
+        L.lre_stream_read.argtypes = [P, SZ, P, P]
+        L.lre_stream_read.restype = I
+        L.lre_stream_copy.argtypes = [P, P, SZ, P]
+        L.lre_stream_copy.restype = I
         L.lre_batch_destroy.argtypes = [P]
         L.lre_batch_destroy.restype = None
         _lib_handle = L
@@ -227,6 +231,25 @@ def signed_sums(counts: torch.Tensor, bases: torch.Tensor, flags: int = 0,
     if check:
         check_flags(dev)
     return out
+
+
+def stream_read(buf: torch.Tensor, sink: torch.Tensor) -> None:
+    """lre_stream_read over the bytes of a contiguous device tensor (diagnostic)."""
+    if not (buf.is_cuda and buf.is_contiguous() and sink.is_cuda and sink.dtype == torch.int32):
+        raise ValueError("buf: contiguous device tensor; sink: int32 device tensor")
+    _ok(lib().lre_stream_read(ctypes.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size(),
+                              ctypes.c_void_p(sink.data_ptr()), ctypes.c_void_p(_stream(buf.device))),
+        "lre_stream_read")
+
+
+def stream_copy(src: torch.Tensor, dst: torch.Tensor) -> None:
+    """lre_stream_copy between two contiguous device tensors of equal size (diagnostic)."""
+    nbytes = src.numel() * src.element_size()
+    if not (src.is_cuda and dst.is_cuda and src.is_contiguous() and dst.is_contiguous()
+            and dst.numel() * dst.element_size() == nbytes):
+        raise ValueError("src, dst: contiguous device tensors of equal size")
+    _ok(lib().lre_stream_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), nbytes,
+                              ctypes.c_void_p(_stream(src.device))), "lre_stream_copy")
 
 
 def set_stage_events(events, device=None):

@@ -45,3 +45,15 @@ def test_estimate_rejects_null_context():
     st = L.lib().lre_estimate(None, 4, ctypes.c_void_p(16), 10, None, ctypes.c_void_p(16),
                               None, None, 0, L.LRE_NO_RHO, None)
     assert st == L.LRE_E_ARG
+
+
+def test_stream_diagnostics_reject_bad_arguments():
+    lib = L.lib()
+    buf = ctypes.c_void_p(4096)
+    assert lib.lre_stream_read(None, 16, buf, None) == L.LRE_E_ARG
+    assert lib.lre_stream_read(buf, 16, None, None) == L.LRE_E_ARG
+    assert lib.lre_stream_read(ctypes.c_void_p(4100), 16, buf, None) == L.LRE_E_ARG   # misaligned
+    assert lib.lre_stream_read(buf, 24, buf, None) == L.LRE_E_ARG                     # not 16-byte units
+    assert lib.lre_stream_copy(buf, None, 16, None) == L.LRE_E_ARG
+    assert lib.lre_stream_copy(buf, ctypes.c_void_p(8200), 16, None) == L.LRE_E_ARG
+    assert lib.lre_stream_read(buf, 0, buf, None) == L.LRE_OK                         # nothing to do
