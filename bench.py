@@ -326,6 +326,7 @@ def bench_batch(args, torch, lre):
                                          f"({t_cpu:.1f} s), extrapolated by 12^n + 8^n terms to all 512 "
                                          f"({t_full:.0f} s)"}
     b.close()
+    out["hbm_measured"] = measured_hbm(torch, lre)
     print(json.dumps(out), flush=True)
 
 
