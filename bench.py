@@ -11,7 +11,7 @@ Prints ONE JSON line with throughput (counts/s over the whole step), the rooflin
 the dominant kernel (the counts pass) measured live with HIP events on the stream it
 runs on, and the CPU oracle timed on a bounded sample of the same workload.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload n14|n12|n8]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload n14|n12|n8|batch|project]
 """
 from __future__ import annotations
 
@@ -111,6 +111,54 @@ def make_workload(name, torch):
                 "shots/basis; coef f64 [4^8] + rho c128 [256^2]")
         return n, torch.from_numpy(c).to(dev), 10_000, None, desc
     raise SystemExit(f"unknown workload {name}")
+
+
+FP64_PEAK_TFS = 78.6
+
+
+def bench_project(args, torch, lre):
+    """Step (iii) (lre_project) at n = 12: mu from 200-shot counts of a Haar pure state,
+    so most eigenvalues are truncated.  The flop count is the usual one of a complex
+    Hermitian eigendecomposition with eigenvectors (reduction to tridiagonal form
+    16/3 d^3, tridiagonal divide and conquer ~4/3 d^3, back-transformation 8 d^3 real
+    flops) plus the reassembly product (8 d^3); the step is dense FP64 library work."""
+    import tomo_inputs.gpu as tg
+    n, shots = 12, 200
+    d = 1 << n
+    counts = tg.haar_multinomial_counts(n, shots, 16043, device="cuda:0")
+    _, mu = lre.estimate(counts, shots)
+    del counts
+    torch.cuda.empty_cache()
+    rho = torch.empty_like(mu)
+    ev = torch.empty(d, dtype=torch.float64, device="cuda:0")
+    ws = torch.empty(lre.lib().lre_project_workspace_bytes(n), dtype=torch.uint8, device="cuda:0")
+    for _ in range(max(1, args.warmup)):
+        lre.project(mu, rho, ev, ws)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        lre.project(mu, rho, ev, ws, check=False)
+    e1.record()
+    torch.cuda.synchronize()
+    lre.check_flags("cuda:0")
+    ms = e0.elapsed_time(e1) / args.steps
+    flops = (16.0 / 3 + 4.0 / 3 + 8.0 + 8.0) * float(d) ** 3
+    kept = int((ev > 0).sum().item())
+    out = {
+        "metric": "step (iii) time (closest physical state)", "value": ms, "unit": "ms",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"n=12: mu from {shots}-shot multinomial counts of a Haar pure state; "
+                               f"complex128 [{d}^2]; {kept} of {d} eigenvalues of mu positive",
+                   "n": n},
+        "roofline": {"bound": "mfma", "achieved": flops / (ms / 1e3) / 1e12, "peak": FP64_PEAK_TFS,
+                     "unit": "TFLOP/s", "frac": flops / (ms / 1e3) / 1e12 / FP64_PEAK_TFS, "traffic": None,
+                     "kernel": "rocsolver_zheevd + spectrum kernel + rocblas_zgemm",
+                     "algorithmic_flops_per_step": flops},
+    }
+    print(f"[bench] project n={n}: {ms:.3f} ms/step", file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
 
 
 def measured_hbm(torch, lre, gib=8, reps=5):
@@ -335,7 +383,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="n14", choices=["n14", "n12", "n8", "batch"])
+    ap.add_argument("--workload", default="n14", choices=["n14", "n12", "n8", "batch", "project"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true",
                     help="time only the headline Walsh path (no MFMA-vs-plain ratio)")
@@ -355,6 +403,8 @@ def main():
     from paper_1602_08604_amd import lre
 
     torch.cuda.set_device(0)
+    if args.workload == "project":
+        return bench_project(args, torch, lre)
     if args.workload == "batch":
         return bench_batch(args, torch, lre)
     t_gen = time.time()

@@ -55,7 +55,8 @@ typedef enum {
   LRE_E_SHOTS = 4,        /* a basis row does not sum to its declared total */
   LRE_E_EMPTY_BASIS = 5,  /* per-basis mode: a basis with zero counts */
   LRE_E_UNSUPPORTED = 6,  /* valid request that this build cannot serve */
-  LRE_E_TIMEOUT = 7       /* a batched run's bounded wait for a dependency expired */
+  LRE_E_TIMEOUT = 7,      /* a batched run's bounded wait for a dependency expired */
+  LRE_E_EIG = 8           /* lre_project: the eigendecomposition did not converge */
 } lre_status;
 
 #define LRE_MAX_QUBITS 14
@@ -208,6 +209,25 @@ lre_status lre_batch_run(lre_batch* plan, void* workspace, size_t workspace_byte
 
 /* Free the plan and its work list (NULL is ignored). */
 void lre_batch_destroy(lre_batch* plan);
+
+/* ---------------------------------------------------------------------------------
+ * Step (iii) (Sec. II): the physical state closest to mu, with the fast algorithm the
+ * paper cites -- eigendecompose mu, move the spectrum onto the probability simplex
+ * (negative eigenvalues removed, the removed mass shared equally over the eigenvalues
+ * kept), reassemble rho = V diag(lambda) V^H.
+ *   mu        : device complex128 [2^n][2^n] row-major, Hermitian with trace 1 (the
+ *               output of lre_estimate); only read.
+ *   rho       : device complex128 [2^n][2^n] row-major, out (positive semidefinite,
+ *               trace 1); must not overlap mu.
+ *   eigvals   : device double [2^n] out, the eigenvalues of mu in ascending order, or
+ *               NULL.
+ *   workspace : at least lre_project_workspace_bytes(n) bytes, 256-byte aligned.
+ * Enqueued on `stream` (eigensolver and product from rocSOLVER / rocBLAS, which may
+ * allocate their own scratch).  A solver failure raises LRE_E_EIG through lre_check
+ * (rho is then 0). */
+size_t lre_project_workspace_bytes(int n);
+lre_status lre_project(lre_ctx* ctx, int n, const void* mu, void* rho, double* eigvals, void* workspace,
+                       size_t workspace_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------------
  * Device streaming rates (diagnostics, not part of the method): plain kernels with

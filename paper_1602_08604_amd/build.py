@@ -13,7 +13,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB_DIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(LIB_DIR, "liblre.so")
-SOURCES = [os.path.join(PKG, "csrc", f) for f in ("lre_abi.hip", "lre_batch.hip", "lre_membench.hip")]
+SOURCES = [os.path.join(PKG, "csrc", f)
+           for f in ("lre_abi.hip", "lre_batch.hip", "lre_project.hip", "lre_membench.hip")]
 DEPS = SOURCES + [os.path.join(PKG, "csrc", f) for f in ("lre_kernels.hpp", "lre_internal.hpp")] + [
     os.path.join(ROOT, "include", "lre.h")]
 
@@ -32,7 +33,7 @@ def build(force: bool = True, verbose: bool = False) -> str:
             os.path.getmtime(LIB) >= os.path.getmtime(d) for d in DEPS):
         return LIB
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, *SOURCES, "-o", tmp]
+    cmd = [HIPCC, *FLAGS, *SOURCES, "-o", tmp, "-lrocsolver", "-lrocblas"]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

@@ -461,6 +461,7 @@ const char* lre_status_str(int s) {
     case LRE_E_EMPTY_BASIS: return "a basis has zero counts";
     case LRE_E_UNSUPPORTED: return "unsupported request";
     case LRE_E_TIMEOUT: return "a batched run's bounded wait expired";
+    case LRE_E_EIG: return "the eigendecomposition of step (iii) did not converge";
     default: return "unknown status";
   }
 }
@@ -486,6 +487,7 @@ void lre_destroy(lre_ctx* ctx) {
   if (!ctx) return;
   DeviceGuard g(ctx->device);
   (void)hipFree(ctx->flags);
+  lre_detail::destroy_blas(ctx->blas);
   delete ctx;
 }
 
@@ -548,6 +550,7 @@ lre_status lre_check(lre_ctx* ctx, void* stream) {
     if (hipMemcpy(ctx->flags, &zero, sizeof zero, hipMemcpyHostToDevice) != hipSuccess) return LRE_E_HIP;
   }
   if (f & FLAG_WAIT) return LRE_E_TIMEOUT;
+  if (f & FLAG_EIG) return LRE_E_EIG;
   if (f & FLAG_ARG) return LRE_E_ARG;
   if (f & FLAG_EMPTY) return LRE_E_EMPTY_BASIS;
   if (f & FLAG_SHOTS) return LRE_E_SHOTS;

@@ -9,9 +9,13 @@ struct lre_ctx {
   uint32_t* flags;              // device word: FLAG_* bits raised by the kernels
   hipEvent_t stage_events[4];   // optional profiling events (lre_set_stage_events)
   int n_stage_events;
+  void* blas = nullptr;         // rocBLAS handle of lre_project, created on first use
 };
 
 namespace lre_detail {
+
+// Releases the rocBLAS handle of a context (lre_project.hip).
+void destroy_blas(void* handle);
 
 inline void record_stage(lre_ctx* ctx, int k, hipStream_t st) {
   if (k < ctx->n_stage_events && ctx->stage_events[k]) (void)hipEventRecord(ctx->stage_events[k], st);

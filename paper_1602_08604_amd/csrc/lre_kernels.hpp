@@ -47,7 +47,7 @@ __host__ __device__ constexpr int64_t ipow3(int k) { return k <= 0 ? 1 : 3 * ipo
 __host__ __device__ constexpr int64_t ipow4(int k) { return k <= 0 ? 1 : 4 * ipow4(k - 1); }
 __host__ __device__ constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
 
-enum : uint32_t { FLAG_SHOTS = 1u, FLAG_EMPTY = 2u, FLAG_ARG = 4u, FLAG_WAIT = 8u };
+enum : uint32_t { FLAG_SHOTS = 1u, FLAG_EMPTY = 2u, FLAG_ARG = 4u, FLAG_WAIT = 8u, FLAG_EIG = 16u };
 
 // What the final pass writes.
 enum class Out : int { Partial = 0, CoefUniform = 1, CoefPerBasis = 2, PauliT = 3 };

@@ -25,6 +25,7 @@ LRE_E_SHOTS = 4
 LRE_E_EMPTY_BASIS = 5
 LRE_E_UNSUPPORTED = 6
 LRE_E_TIMEOUT = 7
+LRE_E_EIG = 8
 
 LRE_NO_RHO = 0x1
 LRE_RHO_FP32 = 0x2
@@ -93,6 +94,10 @@ def lib():
         L.lre_batch_tune.restype = I
         L.lre_batch_run.argtypes = [P, P, SZ, P]
         L.lre_batch_run.restype = I
+        L.lre_project_workspace_bytes.argtypes = [I]
+        L.lre_project_workspace_bytes.restype = SZ
+        L.lre_project.argtypes = [P, I, P, P, P, P, SZ, P]
+        L.lre_project.restype = I
         L.lre_stream_read.argtypes = [P, SZ, P, P]
         L.lre_stream_read.restype = I
         L.lre_stream_copy.argtypes = [P, P, SZ, P]
@@ -188,6 +193,34 @@ def estimate(counts: torch.Tensor, shots: int, n_per_basis: torch.Tensor | None 
     if check:
         check_flags(dev)
     return coef, rho
+
+
+def project(mu: torch.Tensor, rho: torch.Tensor | None = None, eigvals: torch.Tensor | None = None,
+            workspace: torch.Tensor | None = None, check: bool = True):
+    """lre_project (step (iii)): (rho complex128 [d, d] closest physical state, eigenvalues
+    of mu ascending float64 [d])."""
+    if mu.dtype != torch.complex128 or not mu.is_cuda or not mu.is_contiguous() or mu.dim() != 2 \
+            or mu.shape[0] != mu.shape[1]:
+        raise ValueError("mu must be a contiguous complex128 square device tensor")
+    d = mu.shape[0]
+    n = d.bit_length() - 1
+    if d != 1 << n:
+        raise ValueError("mu must be 2^n x 2^n")
+    dev = mu.device
+    if rho is None:
+        rho = torch.empty_like(mu)
+    if eigvals is None:
+        eigvals = torch.empty(d, dtype=torch.float64, device=dev)
+    wsb = lib().lre_project_workspace_bytes(n)
+    if workspace is None:
+        workspace = torch.empty(max(wsb, 1), dtype=torch.uint8, device=dev)
+    st = lib().lre_project(ctypes.c_void_p(context(dev.index)), n, ctypes.c_void_p(mu.data_ptr()),
+                           ctypes.c_void_p(rho.data_ptr()), ctypes.c_void_p(eigvals.data_ptr()),
+                           ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), ctypes.c_void_p(_stream(dev)))
+    _ok(st, "lre_project")
+    if check:
+        check_flags(dev)
+    return rho, eigvals
 
 
 def check_flags(device=None):

@@ -1,0 +1,86 @@
+"""Step (iii) (lre_project) against the oracle (oracle/project.py).
+
+mu comes from lre_estimate on low-shot counts of Haar pure states (so mu has many
+negative eigenvalues and the truncation matters) and of a maximally mixed state; the
+device's eigenvalues and rho are compared with the oracle run on the same mu, and rho is
+checked to be positive semidefinite with unit trace.  A physical input comes back
+unchanged.  Tolerances: eigenvalues and rho within 1e-11 absolute (two different
+eigensolvers in binary64 on matrices of norm <= 1 and size <= 2^10).
+"""
+import numpy as np
+import pytest
+
+from oracle import project as OP
+import tomo_inputs as ti
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+from paper_1602_08604_amd import lre as L  # noqa: E402
+
+DEV = "cuda:0"
+TOL = 1e-11
+
+
+def _mu_from_counts(n, shots, seed):
+    rng = np.random.default_rng(seed)
+    counts = ti.multinomial_counts(ti.born_probs_pure(n, ti.haar_state(n, rng)), shots, rng)
+    _, mu = L.estimate(torch.from_numpy(counts).to(DEV), shots)
+    return mu
+
+
+@pytest.mark.parametrize("n,shots", [(1, 10), (2, 20), (4, 50), (6, 100), (8, 200), (10, 300)])
+def test_project_matches_oracle(n, shots):
+    print(f"[project n={n} shots={shots}]", flush=True)
+    mu = _mu_from_counts(n, shots, 700 + n)
+    rho, ev = L.project(mu)
+    mu_h = mu.cpu().numpy()
+    rho_ref, m_ref, lam_ref = OP.project(mu_h)
+    ev_h = ev.cpu().numpy()
+    rho_h = rho.cpu().numpy()
+    assert np.max(np.abs(ev_h - m_ref)) <= TOL
+    if n >= 2:
+        assert ev_h[0] < 0                          # the truncation has work to do
+    assert np.max(np.abs(rho_h - rho_ref)) <= TOL
+    assert np.max(np.abs(rho_h - rho_h.conj().T)) <= 1e-13
+    assert abs(np.trace(rho_h).real - 1.0) <= 1e-12
+    assert np.linalg.eigvalsh(rho_h).min() >= -1e-12
+
+
+def test_project_keeps_physical_input():
+    print("[project physical input]", flush=True)
+    n = 5
+    rng = np.random.default_rng(77)
+    g = rng.normal(size=(2 ** n, 3)) + 1j * rng.normal(size=(2 ** n, 3))
+    r = g @ g.conj().T
+    r /= np.trace(r).real
+    rho, ev = L.project(torch.from_numpy(r).to(DEV))
+    assert np.max(np.abs(rho.cpu().numpy() - r)) <= TOL
+
+
+def test_project_maximally_mixed_counts():
+    print("[project maximally mixed]", flush=True)
+    n, shots = 7, 30
+    rng = np.random.default_rng(7)
+    p = np.full((3 ** n, 2 ** n), 2.0 ** -n)
+    counts = ti.multinomial_counts(p, shots, rng)
+    _, mu = L.estimate(torch.from_numpy(counts).to(DEV), shots)
+    rho, ev = L.project(mu)
+    rho_ref, m_ref, _ = OP.project(mu.cpu().numpy())
+    assert np.max(np.abs(ev.cpu().numpy() - m_ref)) <= TOL
+    assert np.max(np.abs(rho.cpu().numpy() - rho_ref)) <= TOL
+    # the projection can only bring the estimate closer to the true state (convexity)
+    d = 2 ** n
+    eye = torch.eye(d, dtype=torch.complex128, device=DEV) / d
+    assert ((rho - eye).abs() ** 2).sum().item() <= ((mu - eye).abs() ** 2).sum().item()
+
+
+def test_project_errors():
+    mu = torch.eye(4, dtype=torch.complex128, device=DEV) / 4
+    ws = torch.empty(16, dtype=torch.uint8, device=DEV)
+    with pytest.raises(L.LreError) as e:
+        L.project(mu, workspace=ws)
+    assert e.value.status == L.LRE_E_WORKSPACE
+    with pytest.raises(ValueError):
+        L.project(torch.eye(3, dtype=torch.complex128, device=DEV))
