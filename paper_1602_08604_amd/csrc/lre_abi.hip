@@ -74,7 +74,7 @@ bool make_plan(int n, uint64_t shots, uint32_t flags, Plan& P) {
   const int h = n - P.q1;
   if (h >= kMinHF4 && h <= 4 + kMaxF) {
     // Two passes: 4 qubits (LDS) then the remaining 1..3 in registers, which reads and
-    // writes far less than 3 + 2 + 2 (70 GB instead of 53 GB of partials at n = 14).
+    // writes far less than 3 + 2 + 2 (53 GB instead of 70 GB of partials at n = 14).
     P.npass = 2;
     P.F[0] = 4;
     P.F[1] = h - 4;
@@ -166,8 +166,6 @@ constexpr int fold1_threads() {
   return t > 1024 ? t / 3 : (t < 64 ? 64 : t);
 }
 
-// Waves per SIMD the compiler must leave room for: two blocks per CU when two
-// accumulator tiles fit in LDS (32-bit accumulators), else no constraint.
 // Double-buffered row prefetch with one block per CU (256 registers per lane): faster
 // than two blocks per CU without it for 32-bit tiles too (1.04 vs 1.17 ms at n = 12).
 template <int Q, typename Acc>
@@ -175,6 +173,9 @@ constexpr bool fold1_prefetch() {
   return true;
 }
 
+// Waves per SIMD the compiler must leave room for: two blocks per CU when two
+// accumulator tiles fit in LDS and the kernel runs without the prefetch, else no
+// constraint.
 template <int Q, typename Acc>
 constexpr int fold1_minwaves() {
   constexpr int waves = (fold1_threads<Q>() + 63) / 64;
