@@ -117,16 +117,25 @@ FP64_PEAK_TFS = 78.6
 
 
 def bench_project(args, torch, lre):
-    """Step (iii) (lre_project) at n = 12: mu from 200-shot counts of a Haar pure state,
-    so most eigenvalues are truncated.  The flop count is the usual one of a complex
-    Hermitian eigendecomposition with eigenvectors (reduction to tridiagonal form
-    16/3 d^3, tridiagonal divide and conquer ~4/3 d^3, back-transformation 8 d^3 real
-    flops) plus the reassembly product (8 d^3); the step is dense FP64 library work."""
+    """Step (iii) (lre_project) at n = --project-n: mu from 200-shot counts of a Haar pure
+    state (n <= 12) or from the Philox per-basis workload (n = 13, 14), so that many
+    eigenvalues are truncated.  The flop count is the usual one of a complex Hermitian
+    eigendecomposition with eigenvectors (reduction to tridiagonal form 16/3 d^3,
+    tridiagonal divide and conquer ~4/3 d^3, back-transformation 8 d^3 real flops) plus
+    the reassembly product (8 d^3); the step is dense FP64 library work."""
     import tomo_inputs.gpu as tg
-    n, shots = 12, 200
+    n = args.project_n
     d = 1 << n
-    counts = tg.haar_multinomial_counts(n, shots, 16043, device="cuda:0")
-    _, mu = lre.estimate(counts, shots)
+    if n <= 12:
+        shots = 200
+        counts = tg.haar_multinomial_counts(n, shots, 16043, device="cuda:0")
+        _, mu = lre.estimate(counts, shots)
+        src = f"mu from {shots}-shot multinomial counts of a Haar pure state"
+    else:
+        counts, nb = tg.philox_counts(n, SEED14 if n == 14 else SEED14 + 1, device="cuda:0")
+        _, mu = lre.estimate(counts, 0, n_per_basis=nb)
+        del nb
+        src = "mu from the Philox per-basis workload (i.i.d. U{0..12} counts)"
     del counts
     torch.cuda.empty_cache()
     rho = torch.empty_like(mu)
@@ -149,15 +158,15 @@ def bench_project(args, torch, lre):
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"n=12: mu from {shots}-shot multinomial counts of a Haar pure state; "
-                               f"complex128 [{d}^2]; {kept} of {d} eigenvalues of mu positive",
+        "config": {"workload": f"n={n}: {src}; complex128 [{d}^2]; {kept} of {d} eigenvalues of mu positive",
                    "n": n},
         "roofline": {"bound": "mfma", "achieved": flops / (ms / 1e3) / 1e12, "peak": FP64_PEAK_TFS,
                      "unit": "TFLOP/s", "frac": flops / (ms / 1e3) / 1e12 / FP64_PEAK_TFS, "traffic": None,
                      "kernel": "rocsolver_zheevd + spectrum kernel + rocblas_zgemm",
                      "algorithmic_flops_per_step": flops},
     }
-    print(f"[bench] project n={n}: {ms:.3f} ms/step", file=sys.stderr, flush=True)
+    print(f"[bench] project n={n}: {ms:.3f} ms/step, {kept} of {d} eigenvalues positive", file=sys.stderr,
+          flush=True)
     print(json.dumps(out), flush=True)
 
 
@@ -385,6 +394,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="n14", choices=["n14", "n12", "n8", "batch", "project"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--project-n", type=int, default=12, choices=range(1, 15), metavar="N",
+                    help="qubits of the step-(iii) workload (--workload project)")
     ap.add_argument("--no-compare", action="store_true",
                     help="time only the headline Walsh path (no MFMA-vs-plain ratio)")
     ap.add_argument("--copy-calibration", action="store_true",
