@@ -244,13 +244,16 @@ def cpu_baseline(workload, n, shots, counts_dev, coef_dev, budget_s=12.0):
         threads = 1
     else:
         c = counts_dev.cpu().numpy()
-        idx = rng.integers(0, 4 ** n, size=4096)
-        w = np.array([sum(1 for k in range(n) if (int(j) >> (2 * k)) & 3) for j in idx])
-        t0 = time.perf_counter()
-        oracle.coefs(n, c, shots, idx=idx)
-        t_i = time.perf_counter() - t0
-        visits_i = int(np.sum(3.0 ** (n - w))) * 2 ** n
-        sample = "4096 random coefficients of the full count tensor"
+        # batches of 4096 random coefficients until about 3/4 of the budget is spent
+        while t_i < budget_s * 0.75:
+            idx = rng.integers(0, 4 ** n, size=4096)
+            w = np.array([sum(1 for k in range(n) if (int(j) >> (2 * k)) & 3) for j in idx])
+            t0 = time.perf_counter()
+            oracle.coefs(n, c, shots, idx=idx)
+            t_i += time.perf_counter() - t0
+            visits_i += int(np.sum(3.0 ** (n - w))) * 2 ** n
+            ncoef += len(idx)
+        sample = f"{ncoef} random coefficients of the full count tensor"
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count()))
     # step (ii): sampled entries of eq. (4) on the GPU coefficients
     coef = coef_dev.cpu().numpy() if workload != "n14" else None
