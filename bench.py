@@ -409,8 +409,8 @@ def main():
                          "timed too for the MFMA-vs-plain ratio")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU sharding is a design note only)", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
+              "(sharding across GPUs is not implemented)", file=sys.stderr)
         raise SystemExit(2)
 
     import torch

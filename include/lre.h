@@ -54,7 +54,7 @@ typedef enum {
   LRE_E_HIP = 3,          /* a HIP runtime call failed */
   LRE_E_SHOTS = 4,        /* a basis row does not sum to its declared total */
   LRE_E_EMPTY_BASIS = 5,  /* per-basis mode: a basis with zero counts */
-  LRE_E_UNSUPPORTED = 6,  /* valid request that this build cannot serve */
+  LRE_E_UNSUPPORTED = 6,  /* valid request that the library does not serve */
   LRE_E_TIMEOUT = 7,      /* a batched run's bounded wait for a dependency expired */
   LRE_E_EIG = 8           /* lre_project: the eigendecomposition did not converge */
 } lre_status;

@@ -21,7 +21,7 @@
  * 4^n entries of each Gamma, 2^n nonzero entries per Omega_i), which is the
  * paper's own O(12^n) / O(8^n) evaluation, not a fast transform.
  *
- * Readings where the paper is silent (each is also listed in the design notes):
+ * Readings where the paper is silent:
  *   - basis index b = sum_k b_k 3^{n-k}, b_k in {0:X, 1:Y, 2:Z}, qubit 1 most
  *     significant (mirrors the Pauli index of eq. 5);
  *   - outcome index s = sum_k s_k 2^{n-k}; s_k = 0 is the +1 eigenvector;
