@@ -1,5 +1,6 @@
 """gfx950 (MI355X) library for linear regression estimation (LRE) of quantum states
-from local Pauli measurement counts (arXiv:1602.08604, steps (i) and (ii)).
+from local Pauli measurement counts (arXiv:1602.08604: steps (i) and (ii), and the
+step (iii) projection as a separate call).
 
 The compute path is liblre.so (HIP); ``lre`` is its ctypes binding.
 """
