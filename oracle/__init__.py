@@ -59,6 +59,8 @@ def _load():
         lib.oracle_coef_from_rows.argtypes = [ctypes.c_int, I64, P, P, I64, P]
         lib.oracle_compatible_bases.argtypes = [ctypes.c_int, I64, P]
         lib.oracle_compatible_bases.restype = I64
+        lib.oracle_accumulate_pairs.argtypes = [ctypes.c_int, P, P, P, I64, P, P, P, I64, P]
+        lib.oracle_coef_from_acc.argtypes = [ctypes.c_int, P, P, I64, P]
         lib.oracle_coefs_freq.argtypes = [ctypes.c_int, P, P, I64, P]
         lib.oracle_rho_entries.argtypes = [ctypes.c_int, P, P, P, I64, P]
         lib.oracle_lre.argtypes = [ctypes.c_int, P, ctypes.c_uint64, P, P, P]
@@ -149,6 +151,37 @@ def coef_from_rows(n, i, rows, n_per_basis):
     out = np.zeros(1)
     _check(lib.oracle_coef_from_rows(n, int(i), _ptr(r), _ptr(nb), r.shape[0], _ptr(out)))
     return float(out[0])
+
+
+def accumulate_pairs(n, rows, bases, n_per_basis, pair_row, pair_coef, pair_slot, acc):
+    """Streaming eq. (3), per-basis branch: acc[pair_slot[p]] += S(row pair_row[p],
+    coefficient pair_coef[p]) / N_b for every pair (acc: numpy longdouble, updated in
+    place).  rows: uint16 [nrows, 2^n] of the bases `bases` with totals `n_per_basis`."""
+    lib = _load()
+    r = np.ascontiguousarray(rows, dtype=np.uint16)
+    b = np.ascontiguousarray(bases, dtype=np.int64)
+    nb = np.ascontiguousarray(n_per_basis, dtype=np.uint32)
+    pr = np.ascontiguousarray(pair_row, dtype=np.int64)
+    pc = np.ascontiguousarray(pair_coef, dtype=np.int64)
+    ps = np.ascontiguousarray(pair_slot, dtype=np.int64)
+    if acc.dtype != np.longdouble or not acc.flags.c_contiguous:
+        raise ValueError("acc must be a contiguous numpy longdouble array")
+    if r.shape != (len(b), 2 ** n) or len(nb) != len(b) or not (len(pr) == len(pc) == len(ps)):
+        raise ValueError("inconsistent row / pair arrays")
+    if len(ps) and (ps.min() < 0 or ps.max() >= len(acc)):
+        raise ValueError("pair slot outside acc")
+    _check(lib.oracle_accumulate_pairs(n, _ptr(r), _ptr(b), _ptr(nb), len(b), _ptr(pr), _ptr(pc), _ptr(ps),
+                                       len(ps), _ptr(acc)))
+
+
+def coef_from_acc(n, coefs, acc):
+    """e_i = acc_i / (X^T X)_ii for completed sums (see accumulate_pairs)."""
+    lib = _load()
+    c = np.ascontiguousarray(coefs, dtype=np.int64)
+    a = np.ascontiguousarray(acc, dtype=np.longdouble)
+    out = np.zeros(len(c))
+    _check(lib.oracle_coef_from_acc(n, _ptr(c), _ptr(a), len(c), _ptr(out)))
+    return out
 
 
 def coefs_freq(n, freq, idx=None):

@@ -347,6 +347,65 @@ int oracle_coef_from_rows(int n, int64_t i, const uint16_t* rows, const uint32_t
   return ORACLE_OK;
 }
 
+/* Streaming form of the per-basis branch of eq. (3), for count tensors too large to
+ * hold (the 14-qubit workload): the caller regenerates basis rows in chunks and names
+ * the (row, coefficient) pairs to evaluate; pairs must be compatible (basis b ~ i), which
+ * the caller takes from oracle_compatible_bases.  For pair p, with j = pair_row[p]:
+ *   acc[pair_slot[p]] += (sum_s rows[j][s] prod_k g(a_k, b_k, s_k)) / nb[j]
+ * in long double, pairs added in the order given (the per-pair terms are computed in
+ * parallel, the additions run serially, so the result does not depend on threads).
+ * Each row's total is checked against nb[j].  After every compatible basis of i has
+ * been visited, e_i = acc / (X^T X)_ii (oracle_coef_from_acc). */
+int oracle_accumulate_pairs(int n, const uint16_t* rows, const int64_t* bases, const uint32_t* nb,
+                            int64_t nrows, const int64_t* pair_row, const int64_t* pair_coef,
+                            const int64_t* pair_slot, int64_t npairs, long double* acc) {
+  if (n < 1 || n > ORACLE_MAX_N || !rows || !bases || !nb || !acc || (npairs && (!pair_row || !pair_coef || !pair_slot)))
+    return ORACLE_E_ARG;
+  int st = ensure_tables();
+  if (st) return st;
+  int64_t d = (int64_t)1 << n;
+  int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+  for (int64_t j = 0; j < nrows; ++j) {
+    uint64_t sum = 0;
+    for (int64_t s = 0; s < d; ++s) sum += rows[j * d + s];
+    if (nb[j] == 0) bad |= 2;
+    else if (sum != nb[j]) bad |= 1;
+  }
+  if (bad & 2) return ORACLE_E_EMPTY_BASIS;
+  if (bad & 1) return ORACLE_E_SHOTS;
+  long double* term = (long double*)malloc(sizeof(long double) * (size_t)(npairs > 0 ? npairs : 1));
+  if (!term) return ORACLE_E_ARG;
+#pragma omp parallel for schedule(dynamic, 64) reduction(| : bad)
+  for (int64_t p = 0; p < npairs; ++p) {
+    int64_t j = pair_row[p];
+    if (j < 0 || j >= nrows) { bad |= 1; term[p] = 0.0L; continue; }
+    int a[ORACLE_MAX_N], bd[ORACLE_MAX_N];
+    pauli_digits(n, pair_coef[p], a);
+    int64_t b = bases[j];
+    for (int k = n - 1; k >= 0; --k) { bd[k] = (int)(b % 3); b /= 3; }
+    term[p] = (long double)basis_term(n, rows + j * d, a, bd) / (long double)nb[j];
+  }
+  if (bad) { free(term); return ORACLE_E_ARG; }
+  for (int64_t p = 0; p < npairs; ++p) acc[pair_slot[p]] += term[p];
+  free(term);
+  return ORACLE_OK;
+}
+
+/* e_i from its completed sum over compatible bases (oracle_accumulate_pairs):
+ * (X^T X)^{-1}_ii * acc, the last step of eq. (3). */
+int oracle_coef_from_acc(int n, const int64_t* coefs, const long double* acc, int64_t count, double* e_out) {
+  if (n < 1 || n > ORACLE_MAX_N || !coefs || !acc || !e_out) return ORACLE_E_ARG;
+  int st = ensure_tables();
+  if (st) return st;
+  for (int64_t t = 0; t < count; ++t) {
+    int a[ORACLE_MAX_N];
+    pauli_digits(n, coefs[t], a);
+    e_out[t] = (double)(acc[t] / (long double)xtx_diag(n, a));
+  }
+  return ORACLE_OK;
+}
+
 /* Number of bases compatible with coefficient i, and their indices in increasing
  * order (out may be NULL to only count). */
 int64_t oracle_compatible_bases(int n, int64_t i, int64_t* out) {

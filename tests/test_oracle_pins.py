@@ -248,3 +248,87 @@ def test_coef_from_rows_matches_full():
         assert len(bases) == 3 ** (n - refs.pauli_weight(n, i))
         v = oracle.coef_from_rows(n, i, counts[bases], counts[bases].sum(axis=1))
         assert v == e[i]
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4])
+def test_basis_sums_bruteforce(n):
+    """Per-basis signed sums of eq. (3) (the part sum_s c[b][s] 2^{n/2} gamma_i^(b,s) of one
+    setting, Sec. III): the oracle against a brute-force sum over every outcome with the
+    sign (-1)^popcount(s & m), m the support of i, for every (basis, coefficient) pair.
+    Compatibility (letter a_k = b_k + 1 wherever a_k is not I) and the support mask are
+    derived here from digit arrays, independently of the oracle's own decoding; pairs
+    that are not compatible must give 0 (their Gamma entries vanish)."""
+    rng = np.random.default_rng(200 + n)
+    counts = rng.integers(0, 1000, size=(3 ** n, 2 ** n)).astype(np.uint16)
+    b = np.repeat(np.arange(3 ** n), 4 ** n)
+    i = np.tile(np.arange(4 ** n), 3 ** n)
+    # digit p counts from the least significant position (qubit n - p in the paper's order)
+    bd = np.stack([(b // 3 ** p) % 3 for p in range(n)], axis=1)
+    ad = np.stack([(i >> (2 * p)) & 3 for p in range(n)], axis=1)
+    compat = np.all((ad == 0) | (ad == bd + 1), axis=1)
+    m = np.sum((ad != 0) * (1 << np.arange(n)), axis=1)
+    s = np.arange(2 ** n)
+    par = np.array([bin(v).count("1") & 1 for v in range(2 ** n)])
+    sign = 1 - 2 * par[np.bitwise_and.outer(m, s)]                # (pairs, 2^n)
+    S = np.sum(counts[b].astype(np.int64) * sign, axis=1)
+    S[~compat] = 0
+    got = oracle.basis_sums(n, counts, b, i)
+    np.testing.assert_array_equal(got, S)
+    assert np.count_nonzero(compat) == 6 ** n                    # 2^n supports per basis
+
+
+def _all_pairs(n, idx):
+    pr, pc, ps = [], [], []
+    for t, i in enumerate(idx):
+        b = oracle.compatible_bases(n, int(i))
+        pr.append(b)
+        pc.append(np.full(len(b), i))
+        ps.append(np.full(len(b), t))
+    return np.concatenate(pr), np.concatenate(pc), np.concatenate(ps)
+
+
+@pytest.mark.parametrize("n,p_dep", [(3, 0.0), (5, 0.5)])
+def test_accumulate_pairs_ghz_closed_form(n, p_dep):
+    """Streaming eq. (3) (rows visited in chunks, pairs in an arbitrary order) on exact
+    GHZ counts reproduces the closed-form Pauli expectations."""
+    shots = 2 ** (n + 1)
+    counts = ti.exact_counts(ti.ghz_probs(n, p_dep), shots)
+    idx = np.arange(4 ** n)
+    pr, pc, ps = _all_pairs(n, idx)
+    order = np.random.default_rng(n).permutation(len(pr))
+    pr, pc, ps = pr[order], pc[order], ps[order]
+    acc = np.zeros(len(idx), dtype=np.longdouble)
+    chunk = 7
+    for b0 in range(0, 3 ** n, chunk):
+        bases = np.arange(b0, min(3 ** n, b0 + chunk))
+        sel = (pr >= b0) & (pr < b0 + chunk)
+        oracle.accumulate_pairs(n, counts[bases], bases, counts[bases].sum(axis=1),
+                                pr[sel] - b0, pc[sel], ps[sel], acc)
+    e = oracle.coef_from_acc(n, idx, acc)
+    np.testing.assert_allclose(e, refs.ghz_expectations(n, p_dep), rtol=0, atol=1e-15)
+
+
+def test_accumulate_pairs_bruteforce_least_squares():
+    """Streaming eq. (3) with unequal per-basis totals equals the explicit 6^n x 4^n
+    least-squares solution (numpy.linalg.lstsq) at n = 3."""
+    n = 3
+    rng = np.random.default_rng(33)
+    shots = rng.integers(50, 400, size=3 ** n)
+    counts = ti.multinomial_counts(ti.born_probs_pure(n, ti.haar_state(n, rng)), shots, rng)
+    freq = (counts / counts.sum(axis=1, keepdims=True)).ravel()
+    e_ls, _ = refs.lstsq_estimate(n, freq)
+    idx = np.arange(4 ** n)
+    pr, pc, ps = _all_pairs(n, idx)
+    acc = np.zeros(len(idx), dtype=np.longdouble)
+    oracle.accumulate_pairs(n, counts, np.arange(3 ** n), counts.sum(axis=1), pr, pc, ps, acc)
+    assert np.max(np.abs(oracle.coef_from_acc(n, idx, acc) - e_ls)) <= 1e-12
+
+
+def test_accumulate_pairs_errors():
+    n = 2
+    counts = ti.maximally_mixed_counts(n, 3)
+    acc = np.zeros(4, dtype=np.longdouble)
+    with pytest.raises(oracle.OracleError):       # declared total differs from the row
+        oracle.accumulate_pairs(n, counts, np.arange(9), np.full(9, 11), [0], [0], [0], acc)
+    with pytest.raises(oracle.OracleError):       # row index outside the chunk
+        oracle.accumulate_pairs(n, counts, np.arange(9), np.full(9, 12), [9], [0], [0], acc)
