@@ -62,6 +62,8 @@ def _load():
         lib.oracle_accumulate_pairs.argtypes = [ctypes.c_int, P, P, P, I64, P, P, P, I64, P]
         lib.oracle_coef_from_acc.argtypes = [ctypes.c_int, P, P, I64, P]
         lib.oracle_coefs_freq.argtypes = [ctypes.c_int, P, P, I64, P]
+        lib.oracle_povm_coefs.argtypes = [ctypes.c_int, P, P, P, I64, P]
+        lib.oracle_povm_coefs_freq.argtypes = [ctypes.c_int, P, P, P, I64, P]
         lib.oracle_rho_entries.argtypes = [ctypes.c_int, P, P, P, I64, P]
         lib.oracle_lre.argtypes = [ctypes.c_int, P, ctypes.c_uint64, P, P, P]
         lib.oracle_op_count_step1.restype = ctypes.c_uint64
@@ -181,6 +183,34 @@ def coef_from_acc(n, coefs, acc):
     a = np.ascontiguousarray(acc, dtype=np.longdouble)
     out = np.zeros(len(c))
     _check(lib.oracle_coef_from_acc(n, _ptr(c), _ptr(a), len(c), _ptr(out)))
+    return out
+
+
+def povm_coefs(n, counts, G, idx=None):
+    """Eq. (3) for the reduced set of 4^n product operators with per-qubit Pauli components
+    G[j][a] = Tr(E_j sigma_a) (4 x 4, invertible): e_i = 2^{n/2} theta_i from counts[4^n]
+    (outcome j = sum_k j_k 4^{n-k}), p = c / sum(c).  n <= 8."""
+    lib = _load()
+    c = np.ascontiguousarray(counts, dtype=np.uint16).ravel()
+    if c.size != 4 ** n:
+        raise ValueError("counts must hold 4^n outcomes")
+    g = np.ascontiguousarray(G, dtype=np.float64).reshape(4, 4)
+    ix = _idx(idx)
+    out = np.zeros(4 ** n if ix is None else len(ix))
+    _check(lib.oracle_povm_coefs(n, _ptr(c), _ptr(g), _ptr(ix), 0 if ix is None else len(ix), _ptr(out)))
+    return out
+
+
+def povm_coefs_freq(n, freq, G, idx=None):
+    """povm_coefs with given frequencies p[4^n] (float64)."""
+    lib = _load()
+    f = np.ascontiguousarray(freq, dtype=np.float64).ravel()
+    if f.size != 4 ** n:
+        raise ValueError("freq must hold 4^n outcomes")
+    g = np.ascontiguousarray(G, dtype=np.float64).reshape(4, 4)
+    ix = _idx(idx)
+    out = np.zeros(4 ** n if ix is None else len(ix))
+    _check(lib.oracle_povm_coefs_freq(n, _ptr(f), _ptr(g), _ptr(ix), 0 if ix is None else len(ix), _ptr(out)))
     return out
 
 

@@ -517,3 +517,125 @@ int oracle_lre(int n, const uint16_t* counts, uint64_t shots, const uint32_t* nb
 void oracle_reset_op_counts(void) { ops_step1 = 0; ops_step2 = 0; }
 uint64_t oracle_op_count_step1(void) { return ops_step1; }
 uint64_t oracle_op_count_step2(void) { return ops_step2; }
+
+/* ---- reduced operator set (Sec. VI): 4^n product operators instead of 6^n ----
+ *
+ * The summary of the paper notes that 4^n measured operators instead of the 6^n Pauli
+ * projectors suffice (and lower the cost).  The set is not named there; this oracle takes
+ * any per-qubit set of four operators E_0..E_3 given by their Pauli components
+ *   G[j][a] = Tr(E_j sigma_a),   a = 0..3 (I, X, Y, Z),
+ * and the n-qubit operators E_j = (x)_k E_{j_k}, j = sum_k j_k 4^{n-k}.  Eq. (2) gives
+ *   Gamma^(j)_i = Tr(E_j Omega_i) = 2^{-n/2} prod_k G[j_k][a_k],
+ * so X^T X = sum_j Gamma^(j) Gamma^(j)^T = 2^{-n} (x)_k (G^T G)  (the tensor structure of
+ * Sec. III), and eq. (3) is
+ *   theta_i = sum_i' (X^T X)^{-1}_{i i'} sum_j p_j Gamma^(j)_{i'},
+ * evaluated here term by term over all i' and j (16^n each; fine for n <= 6).
+ * (G^T G)^{-1} is the inverse of a 4 x 4 matrix, by Gauss-Jordan elimination with
+ * partial pivoting in long double.  p_j = c_j / N with N = sum_j c_j (one setting
+ * measures every outcome at once).  Returns e_i = 2^{n/2} theta_i. */
+
+static int inverse4(const long double m_in[4][4], long double inv[4][4]) {
+  long double m[4][8];
+  for (int r = 0; r < 4; ++r)
+    for (int c = 0; c < 8; ++c) m[r][c] = c < 4 ? m_in[r][c] : (long double)(c - 4 == r);
+  for (int c = 0; c < 4; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < 4; ++r)
+      if (fabsl(m[r][c]) > fabsl(m[piv][c])) piv = r;
+    if (fabsl(m[piv][c]) < 1e-12L) return ORACLE_E_ARG;   /* not invertible */
+    if (piv != c)
+      for (int k = 0; k < 8; ++k) { long double t = m[c][k]; m[c][k] = m[piv][k]; m[piv][k] = t; }
+    long double d = m[c][c];
+    for (int k = 0; k < 8; ++k) m[c][k] /= d;
+    for (int r = 0; r < 4; ++r)
+      if (r != c) {
+        long double f = m[r][c];
+        for (int k = 0; k < 8; ++k) m[r][k] -= f * m[c][k];
+      }
+  }
+  for (int r = 0; r < 4; ++r)
+    for (int c = 0; c < 4; ++c) inv[r][c] = m[r][c + 4];
+  return ORACLE_OK;
+}
+
+static int povm_coefs_core(int n, const long double* p, const double* G, const int64_t* idx, int64_t nidx,
+                           double* e_out);
+
+int oracle_povm_coefs(int n, const uint16_t* counts, const double* G, const int64_t* idx, int64_t nidx,
+                      double* e_out) {
+  if (n < 1 || n > 8 || !counts || !G || !e_out) return ORACLE_E_ARG;
+  int64_t D2 = ipow(4, n);
+  uint64_t N = 0;
+  for (int64_t j = 0; j < D2; ++j) N += counts[j];
+  if (N == 0) return ORACLE_E_EMPTY_BASIS;
+  long double* p = (long double*)malloc(sizeof(long double) * (size_t)D2);
+  if (!p) return ORACLE_E_ARG;
+  for (int64_t j = 0; j < D2; ++j) p[j] = (long double)counts[j] / (long double)N;
+  int st = povm_coefs_core(n, p, G, idx, nidx, e_out);
+  free(p);
+  return st;
+}
+
+/* The same with given frequencies p_j (exact probabilities in the pin tests). */
+int oracle_povm_coefs_freq(int n, const double* freq, const double* G, const int64_t* idx, int64_t nidx,
+                           double* e_out) {
+  if (n < 1 || n > 8 || !freq || !G || !e_out) return ORACLE_E_ARG;
+  int64_t D2 = ipow(4, n);
+  long double* p = (long double*)malloc(sizeof(long double) * (size_t)D2);
+  if (!p) return ORACLE_E_ARG;
+  for (int64_t j = 0; j < D2; ++j) p[j] = freq[j];
+  int st = povm_coefs_core(n, p, G, idx, nidx, e_out);
+  free(p);
+  return st;
+}
+
+static int povm_coefs_core(int n, const long double* p, const double* G, const int64_t* idx, int64_t nidx,
+                           double* e_out) {
+  int64_t D2 = ipow(4, n);
+  long double g[4][4], gtg[4][4], A[4][4];
+  for (int j = 0; j < 4; ++j)
+    for (int a = 0; a < 4; ++a) g[j][a] = G[4 * j + a];
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) {
+      gtg[a][b] = 0;
+      for (int j = 0; j < 4; ++j) gtg[a][b] += g[j][a] * g[j][b];
+    }
+  if (inverse4(gtg, A)) return ORACLE_E_ARG;
+  /* y_i' = sum_j p_j Gamma^(j)_{i'} * 2^{n/2} (the 2^{-n/2} of Gamma kept aside) */
+  long double* y = (long double*)malloc(sizeof(long double) * (size_t)D2);
+  if (!y) return ORACLE_E_ARG;
+#pragma omp parallel for schedule(static)
+  for (int64_t ip = 0; ip < D2; ++ip) {
+    int a[ORACLE_MAX_N];
+    pauli_digits(n, ip, a);
+    long double acc = 0.0L;
+    for (int64_t j = 0; j < D2; ++j) {
+      int jd[ORACLE_MAX_N];
+      pauli_digits(n, j, jd);   /* same base-4 digit order for outcomes */
+      long double prod = 1.0L;
+      for (int k = 0; k < n; ++k) prod *= g[jd[k]][a[k]];
+      acc += p[j] * prod;
+    }
+    y[ip] = acc;
+  }
+  /* theta_i = sum_i' (X^T X)^{-1}_{ii'} y_{i'} 2^{-n/2}, (X^T X)^{-1} = 2^n (x) A;
+   * e_i = 2^{n/2} theta_i = 2^n sum_i' prod_k A[a_k][a'_k] y_i' */
+  int64_t cnt = idx ? nidx : D2;
+#pragma omp parallel for schedule(static)
+  for (int64_t t = 0; t < cnt; ++t) {
+    int64_t i = idx ? idx[t] : t;
+    int a[ORACLE_MAX_N];
+    pauli_digits(n, i, a);
+    long double acc = 0.0L;
+    for (int64_t ip = 0; ip < D2; ++ip) {
+      int b[ORACLE_MAX_N];
+      pauli_digits(n, ip, b);
+      long double prod = 1.0L;
+      for (int k = 0; k < n; ++k) prod *= A[a[k]][b[k]];
+      acc += prod * y[ip];
+    }
+    e_out[t] = (double)(ldexpl(acc, n));
+  }
+  free(y);
+  return ORACLE_OK;
+}
