@@ -64,6 +64,7 @@ def _load():
         lib.oracle_coefs_freq.argtypes = [ctypes.c_int, P, P, I64, P]
         lib.oracle_povm_coefs.argtypes = [ctypes.c_int, P, P, P, I64, P]
         lib.oracle_povm_coefs_freq.argtypes = [ctypes.c_int, P, P, P, I64, P]
+        lib.oracle_povm_coefs_direct.argtypes = [ctypes.c_int, P, P, P, I64, P, P]
         lib.oracle_rho_entries.argtypes = [ctypes.c_int, P, P, P, I64, P]
         lib.oracle_lre.argtypes = [ctypes.c_int, P, ctypes.c_uint64, P, P, P]
         lib.oracle_op_count_step1.restype = ctypes.c_uint64
@@ -199,6 +200,22 @@ def povm_coefs(n, counts, G, idx=None):
     out = np.zeros(4 ** n if ix is None else len(ix))
     _check(lib.oracle_povm_coefs(n, _ptr(c), _ptr(g), _ptr(ix), 0 if ix is None else len(ix), _ptr(out)))
     return out
+
+
+def povm_coefs_direct(n, counts, G, idx):
+    """Selected coefficients of povm_coefs, each from the O(n 4^n) entrywise product of
+    the Kronecker-structured (X^T X)^{-1} row and Gamma^(j) (any n); also returns the
+    scale 2^n sum_j p_j prod_k |w[a_k][j_k]| of each coefficient's terms."""
+    lib = _load()
+    c = np.ascontiguousarray(counts, dtype=np.uint16).ravel()
+    if c.size != 4 ** n:
+        raise ValueError("counts must hold 4^n outcomes")
+    g = np.ascontiguousarray(G, dtype=np.float64).reshape(4, 4)
+    ix = np.ascontiguousarray(idx, dtype=np.int64)
+    out = np.zeros(len(ix))
+    cond = np.zeros(len(ix))
+    _check(lib.oracle_povm_coefs_direct(n, _ptr(c), _ptr(g), _ptr(ix), len(ix), _ptr(out), _ptr(cond)))
+    return out, cond
 
 
 def povm_coefs_freq(n, freq, G, idx=None):

@@ -639,3 +639,53 @@ static int povm_coefs_core(int n, const long double* p, const double* G, const i
   free(y);
   return ORACLE_OK;
 }
+
+/* Reduced operator set, selected coefficients of eq. (3) without the 4^n-long
+ * intermediate: row i of (X^T X)^{-1} = 2^n (x)_k A (A = (G^T G)^{-1}) times
+ * Gamma^(j) = 2^{-n/2} (x)_k G[j_k][.] is the product over qubits of the one-qubit
+ * row-times-vector sums w[a][j] = sum_a' A[a][a'] G[j][a'] (a Kronecker product times
+ * a Kronecker product, taken entry by entry), so
+ *   e_i = 2^{n/2} theta_i = 2^n sum_j p_j prod_k w[a_k][j_k],
+ * O(n 4^n) per coefficient, for n too large for the full O(16^n) evaluation.
+ * cond_out (optional): 2^n sum_j p_j prod_k |w[a_k][j_k]|, the scale against which
+ * rounding in any summation order is measured. */
+int oracle_povm_coefs_direct(int n, const uint16_t* counts, const double* G, const int64_t* idx, int64_t nidx,
+                             double* e_out, double* cond_out) {
+  if (n < 1 || n > ORACLE_MAX_N || !counts || !G || !idx || !e_out) return ORACLE_E_ARG;
+  int64_t D2 = ipow(4, n);
+  uint64_t N = 0;
+  for (int64_t j = 0; j < D2; ++j) N += counts[j];
+  if (N == 0) return ORACLE_E_EMPTY_BASIS;
+  long double g[4][4], gtg[4][4], A[4][4], w[4][4];
+  for (int j = 0; j < 4; ++j)
+    for (int a = 0; a < 4; ++a) g[j][a] = G[4 * j + a];
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) {
+      gtg[a][b] = 0;
+      for (int j = 0; j < 4; ++j) gtg[a][b] += g[j][a] * g[j][b];
+    }
+  if (inverse4(gtg, A)) return ORACLE_E_ARG;
+  for (int a = 0; a < 4; ++a)
+    for (int j = 0; j < 4; ++j) {
+      w[a][j] = 0;
+      for (int c = 0; c < 4; ++c) w[a][j] += A[a][c] * g[j][c];
+    }
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t t = 0; t < nidx; ++t) {
+    int a[ORACLE_MAX_N];
+    pauli_digits(n, idx[t], a);
+    long double acc = 0.0L, cond = 0.0L;
+    for (int64_t j = 0; j < D2; ++j) {
+      if (!counts[j]) continue;
+      int jd[ORACLE_MAX_N];
+      pauli_digits(n, j, jd);
+      long double prod = 1.0L;
+      for (int k = 0; k < n; ++k) prod *= w[a[k]][jd[k]];
+      acc += (long double)counts[j] * prod;
+      cond += (long double)counts[j] * fabsl(prod);
+    }
+    e_out[t] = (double)(ldexpl(acc / (long double)N, n));
+    if (cond_out) cond_out[t] = (double)(ldexpl(cond / (long double)N, n));
+  }
+  return ORACLE_OK;
+}

@@ -98,3 +98,42 @@ def test_povm_errors():
         oracle.povm_coefs(2, np.ones(16, dtype=np.uint16), G)
     with pytest.raises(oracle.OracleError):
         oracle.povm_coefs(2, np.zeros(16, dtype=np.uint16), components(tetra_ops()))
+
+
+@pytest.mark.parametrize("which", ["tetra", "pauli_subset"])
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5])
+def test_povm_direct_matches_full(which, n):
+    """The selected-coefficient entry (entrywise Kronecker row times Gamma^(j)) equals the
+    full evaluation, which the least-squares pins above fix; its scale bounds |e|."""
+    G = components(tetra_ops() if which == "tetra" else pauli_subset_ops())
+    rng = np.random.default_rng(60 + n)
+    c = rng.integers(0, 300, size=4 ** n).astype(np.uint16)
+    idx = np.arange(4 ** n)
+    e_full = oracle.povm_coefs(n, c, G)
+    e, cond = oracle.povm_coefs_direct(n, c, G, idx)
+    assert np.max(np.abs(e - e_full) / np.maximum(cond, 1.0)) <= 1e-14
+    assert np.all(np.abs(e) <= cond * (1 + 1e-14))
+    if which == "tetra":                 # a complete POVM: the frequencies fix the trace
+        assert abs(e[0] - 1) <= 1e-14
+
+
+def test_povm_direct_exact_recovery_product_state():
+    """A product state measured with the tetrahedral POVM: outcome probabilities factor,
+    and with the Bloch vector (sqrt3/4, 0, 0) on every qubit each one-qubit probability is
+    5/16 or 3/16, so counts 5^m 3^(n-m) are exact; e_i = prod_k (Bloch vector components),
+    i.e. 1 for I, sqrt3/4 for X and 0 for Y, Z letters."""
+    n = 6
+    G = components(tetra_ops())
+    j = np.arange(4 ** n)
+    m = np.zeros(4 ** n, dtype=np.int64)
+    for k in range(n):
+        m += ((j >> (2 * k)) & 3) < 2        # outcomes 0, 1 of the frame have r_x = +1
+    c = (5 ** m * 3 ** (n - m)).astype(np.uint16)
+    rng = np.random.default_rng(6)
+    idx = np.concatenate([[0], rng.integers(0, 4 ** n, 200)])
+    e, _ = oracle.povm_coefs_direct(n, c, G, idx)
+    want = np.ones(len(idx))
+    for k in range(n):
+        a = (idx >> (2 * k)) & 3
+        want *= np.where(a == 0, 1.0, np.where(a == 1, np.sqrt(3) / 4, 0.0))
+    assert np.max(np.abs(e - want)) <= 1e-14
