@@ -26,7 +26,8 @@
  * Conventions common to every entry point:
  *   - Calls enqueue work on `stream` (a hipStream_t; NULL = default stream) and return
  *     without synchronising.  No entry point allocates device memory except
- *     lre_create (a 64-byte flag word) and lre_batch_plan (its work list).
+ *     lre_create (a 64-byte flag word) and lre_batch_plan (the work list);
+ *     lre_project's solver libraries allocate their own scratch.
  *   - Host-checkable problems (bad n, NULL or misaligned pointers, workspace too
  *     small) return an error before anything is launched.
  *   - Data-dependent problems are recorded in the context's device flag word and
@@ -154,9 +155,13 @@ lre_status lre_signed_sums(lre_ctx* ctx, int n, const uint16_t* counts, const in
 typedef struct {
   int n;                   /* 1 <= n <= LRE_BATCH_MAX_QUBITS */
   const uint16_t* counts;  /* device uint16 [3^n][2^n], 16-byte aligned */
-  uint64_t shots;          /* per-basis total, > 0, with 3^n * shots < 2^31 (checked per
-                              basis like lre_estimate; per-basis totals are not
-                              supported in a batch: LRE_E_UNSUPPORTED) */
+  uint64_t shots;          /* > 0: every basis totals exactly `shots`, with
+                              3^n * shots < 2^31 (integer branch, checked per basis);
+                              == 0: per-basis totals N_b (binary64 branch), as in
+                              lre_estimate */
+  const uint32_t* n_per_basis; /* shots == 0 only: device uint32 [3^n], 4-byte aligned,
+                              checked against the row sums, or NULL to take the row
+                              sums (one extra pass over the instance's counts) */
   double* coef;            /* device double [4^n], 8-byte aligned */
   void* rho;               /* device complex [2^n][2^n], 16-byte aligned; unused with
                               LRE_NO_RHO */
@@ -177,9 +182,12 @@ typedef struct lre_batch lre_batch;
 
 /* Plan a batch of `count` instances (count >= 1).  flags: LRE_NO_RHO | LRE_RHO_FP32
  * (applied to every instance).  The instance array is copied; the buffers it points
- * to must stay valid while the plan is used.  Allocates the device work list.
- * Errors: LRE_E_ARG (bad instance: n, pointer, alignment, shots == 0 or too large),
- * LRE_E_UNSUPPORTED, LRE_E_HIP. */
+ * to must stay valid while the plan is used.  Allocates the device work list (once:
+ * lre_batch_set_tiles and lre_batch_tune reuse it).
+ * A plan with a per-basis instance (shots == 0) runs one workgroup per compute unit
+ * (its binary64 accumulators fill the LDS), whatever workers_per_cu says.
+ * Errors: LRE_E_ARG (bad instance: n < 1, pointer, alignment, shots too large),
+ * LRE_E_UNSUPPORTED (n > LRE_BATCH_MAX_QUBITS), LRE_E_HIP. */
 lre_status lre_batch_plan(lre_ctx* ctx, const lre_instance* inst, int count, uint32_t flags,
                           lre_batch** plan_out);
 
@@ -188,13 +196,19 @@ lre_status lre_batch_plan(lre_ctx* ctx, const lre_instance* inst, int count, uin
 size_t lre_batch_workspace_bytes(const lre_batch* plan);
 
 /* Replace the plan's work-item shape and rebuild its work list (synchronous: waits
- * for the upload).  Errors: LRE_E_ARG for out-of-range fields, LRE_E_HIP. */
+ * for the device to be idle, then uploads).  The list keeps its device address for
+ * the plan's lifetime (it is allocated once by lre_batch_plan, at the length of the
+ * longest shape) and the persistent kernel reads the item count from device memory,
+ * so an lre_batch_run captured into a HIP graph before a retune stays valid: its
+ * replays run the current list (with the grid and per-CU worker count of the
+ * captured launch).  Errors: LRE_E_ARG for out-of-range fields, LRE_E_HIP. */
 lre_status lre_batch_set_tiles(lre_batch* plan, const lre_batch_tiles* tiles);
 
 /* The plan's current work-item shape and work-item count. */
 lre_status lre_batch_get_tiles(const lre_batch* plan, lre_batch_tiles* tiles, int* num_items);
 
-/* Autotuner: runs the batch (lre_batch_run) for each of 72 candidate work-item shapes,
+/* Autotuner: runs the batch (lre_batch_run) for each of 72 candidate work-item shapes
+ * (36 for a plan with per-basis instances, which run one workgroup per CU),
  * `reps` timed runs each after one warm-up, keeps the fastest shape and returns its
  * mean time in *best_ms (may be NULL).  Synchronous on `stream`; overwrites the
  * instances' outputs.  workspace as for lre_batch_run. */
@@ -209,6 +223,94 @@ lre_status lre_batch_run(lre_batch* plan, void* workspace, size_t workspace_byte
 
 /* Free the plan and its work list (NULL is ignored). */
 void lre_batch_destroy(lre_batch* plan);
+
+/* ---------------------------------------------------------------------------------
+ * Streamed estimation: counts delivered slab by slab, for instances whose counts do not
+ * fit device memory (n = 15 holds 940 GB of counts), the way the paper fed its GPU one
+ * group of measurement data at a time (Sec. III storage, Sec. IV GPU scheme).  Results
+ * are those of lre_estimate: bit-identical coefficients with uniform shots, binary64
+ * sums (order-dependent rounding) with per-basis totals.
+ *
+ * Slab k (0 <= k < 3^h) holds the 3^(n-h) consecutive bases k*3^(n-h) .. (k+1)*3^(n-h)-1,
+ * i.e. the bases whose top h qubits carry the letters of k's base-3 digits: device (or,
+ * for lre_stream_push_host, host) uint16 [3^(n-h)][2^n], rows as in `counts` above.
+ * Each slab is cut into its 2^h outcome segments (fixed outcome bits of the top h
+ * qubits); a segment goes through the passes of an (n-h)-qubit instance, whose rows are
+ * read with the stride of the full rows, and the top h qubits are folded into `coef`,
+ * which accumulates over the slabs; lre_stream_finish divides by (X^T X)_ii and runs
+ * step (ii).  Slabs may come in any order, each exactly once.  Every call of one
+ * stream object must be ordered on one HIP stream and use the same workspace.
+ */
+#define LRE_STREAM_MAX_QUBITS 15
+#define LRE_STREAM_HOST 0x8u  /* lre_stream_create: reserve a staging slab for push_host */
+
+typedef struct lre_stream lre_stream;
+
+/* Plan a streamed estimate of n qubits with slabs fixed by the top h qubits:
+ * 1 <= h <= 6, 8 <= n - h <= LRE_MAX_QUBITS, n <= LRE_STREAM_MAX_QUBITS.  shots: as in
+ * lre_estimate (0 = per-basis totals).  flags: LRE_NO_RHO | LRE_RHO_FP32 | LRE_WHT_MFMA
+ * | LRE_STREAM_HOST.  Host memory only (one event is created).  Errors: LRE_E_ARG,
+ * LRE_E_HIP. */
+lre_status lre_stream_create(lre_ctx* ctx, int n, int h, uint64_t shots, uint32_t flags, lre_stream** out);
+
+/* Device workspace bytes every call of the stream object needs (256-byte aligned,
+ * caller-owned, one buffer for all calls): one segment's pass buffers, the 2^h segment
+ * sums, their row-sum parts, the staging slab with LRE_STREAM_HOST, and step (ii)'s
+ * intermediate (16 * 4^n bytes, aliased onto the rest).  0 for NULL. */
+size_t lre_stream_workspace_bytes(const lre_stream* s);
+
+/* Start an estimate: coef (device double [4^n], 8-byte aligned) becomes the accumulator
+ * and is cleared (a fill kernel on `stream`); forgets earlier slabs.  Errors: LRE_E_ARG,
+ * LRE_E_WORKSPACE, LRE_E_HIP. */
+lre_status lre_stream_begin(lre_stream* s, double* coef, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Add slab `slab` from device memory (16-byte aligned; n_per_basis: device uint32
+ * [3^(n-h)] of the slab's totals or NULL for the row sums, read only with shots == 0).
+ * Enqueued on `stream`; the slab's buffers must stay unchanged until the stream has
+ * passed its kernels.  Data errors (totals, empty bases) go to the context's flag word.
+ * Errors: LRE_E_ARG (no lre_stream_begin, slab out of range or already pushed, pointer),
+ * LRE_E_WORKSPACE, LRE_E_HIP. */
+lre_status lre_stream_push(lre_stream* s, int64_t slab, const uint16_t* counts, const uint32_t* n_per_basis,
+                           void* workspace, size_t workspace_bytes, void* stream);
+
+/* As lre_stream_push, for a slab in host memory (pinned memory copies at the link's
+ * full rate): copied on `stream` into the workspace's staging slab (the stream object
+ * must have been created with LRE_STREAM_HOST), then processed there.  Returns once the
+ * copies have completed, so the host buffers may be refilled at once while the slab's
+ * kernels run.  Errors as lre_stream_push. */
+lre_status lre_stream_push_host(lre_stream* s, int64_t slab, const uint16_t* counts, const uint32_t* n_per_basis,
+                                void* workspace, size_t workspace_bytes, void* stream);
+
+/* After all 3^h slabs: coef[i] /= 3^{n-w(i)} (times shots in uniform mode), then step
+ * (ii) into rho (device complex [2^n][2^n], 16-byte aligned) unless LRE_NO_RHO.
+ * Enqueued on `stream`.  Errors: LRE_E_ARG (a slab missing, no begin, rho), LRE_E_WORKSPACE,
+ * LRE_E_HIP. */
+lre_status lre_stream_finish(lre_stream* s, void* rho, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Destroy a stream object (NULL is ignored). */
+void lre_stream_destroy(lre_stream* s);
+
+/* ---------------------------------------------------------------------------------
+ * Reduced measurement set (Sec. VI): instead of the 3^n Pauli bases, one
+ * informationally complete set of four operators E_0..E_3 per qubit (the same set on
+ * every qubit, e.g. a four-outcome POVM), i.e. 4^n product operators.  The paper names
+ * no set; the caller gives it by its Pauli components.  Eq. (3) is then
+ *   e = 2^{n/2} theta = ((x)_k M) p,  M = 2 (G^T G)^{-1} G^T,  p_j = c_j / N,
+ * since Gamma^(j) is the tensor product of the rows G[j_k][.] / sqrt 2 and
+ * X^T X = 2^-n (x)_k G^T G; step (ii) is eq. (4) on e as for the Pauli bases.
+ *   counts : device uint16 [4^n], outcome j = sum_k j_k 4^{n-k} (qubit 1 most
+ *            significant), 16-byte aligned; N = sum of all counts.
+ *   G      : device double [4][4] row-major, G[j][a] = Tr(E_j sigma_a) (sigma_0 = I,
+ *            then X, Y, Z); G^T G must be invertible (else LRE_E_ARG through lre_check
+ *            and coef = 0).  N = 0 raises LRE_E_EMPTY_BASIS through lre_check.
+ *   coef   : device double [4^n], e_i in the layout of lre_estimate (binary64; M and
+ *            the mode products in binary64, one division by N at the end).
+ *   rho    : as lre_estimate; flags LRE_NO_RHO | LRE_RHO_FP32.
+ *   workspace : at least lre_povm_workspace_bytes(n, flags) bytes, 256-byte aligned.
+ * 1 <= n <= LRE_MAX_QUBITS.  Enqueued on `stream`. */
+size_t lre_povm_workspace_bytes(int n, uint32_t flags);
+lre_status lre_povm_estimate(lre_ctx* ctx, int n, const uint16_t* counts, const double* G, double* coef, void* rho,
+                             void* workspace, size_t workspace_bytes, uint32_t flags, void* stream);
 
 /* ---------------------------------------------------------------------------------
  * Step (iii) (Sec. II): the physical state closest to mu, with the fast algorithm the

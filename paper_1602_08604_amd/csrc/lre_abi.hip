@@ -6,10 +6,13 @@
 #include <climits>
 #include <cstdint>
 #include <cstring>
+#include <new>
+#include <vector>
 
 #include "lre.h"
 #include "lre_internal.hpp"
 #include "lre_kernels.hpp"
+#include "lre_povm.hpp"
 
 using namespace lre;
 using lre_detail::aligned;
@@ -147,6 +150,7 @@ int64_t resident_blocks(K kernel, int threads, int64_t lds_bytes) {
 struct Fold1Args {
   const uint16_t* counts;
   int n, chunks;
+  int lrow;             // log2 of the row stride of counts (n for a whole instance)
   const uint32_t* nb;   // per-basis totals (MFMA kernel)
   const double* inv;    // their reciprocals (streaming kernel)
   void* out;
@@ -190,7 +194,7 @@ void launch_fold1(const Fold1Args& a) {
   hipLaunchKernelGGL((fold_counts_stream_kernel<Q, TH, Acc, PB, M, MAD24, fold1_minwaves<Q, Acc>(),
                                                fold1_prefetch<Q, Acc>()>),
                      dim3((unsigned)a.blocks), dim3(TH), 0,
-                     a.st, a.counts, a.n, a.chunks, a.inv, a.out, a.rowpart, a.shots);
+                     a.st, a.counts, a.n, a.chunks, a.inv, a.out, a.rowpart, a.shots, a.lrow);
 }
 
 // The lane butterflies of 32-bit sums use a 24-bit multiply-add when every value they
@@ -237,7 +241,7 @@ template <typename Acc, bool PB, Out M>
 void launch_fold1_mfma(const Fold1Args& a) {
   constexpr int TH = sizeof(Acc) == 8 ? 512 : 256;
   hipLaunchKernelGGL((fold_counts_mfma_kernel<TH, Acc, PB, M>), dim3((unsigned)a.blocks), dim3(TH), 0,
-                     a.st, a.counts, a.n, a.chunks, a.nb, a.out, a.rowpart, a.shots);
+                     a.st, a.counts, a.n, a.chunks, a.nb, a.out, a.rowpart, a.shots, a.lrow);
 }
 
 bool fold1_mfma(Ty t, bool pb, Out m, const Fold1Args& a) {
@@ -382,36 +386,38 @@ void launch_rho(const Plan& P, const double* coef, void* rho, char* ws, hipStrea
     }
     return;
   }
-  // 5..8 high qubits: two register phases with one LDS transpose
+  // 5..9 high qubits: two register phases with one LDS transpose
   switch (n - kRhoJ) {
     case 5: launch_rho_high2<5, OutT>(tmp, rho, n, st); break;
     case 6: launch_rho_high2<6, OutT>(tmp, rho, n, st); break;
     case 7: launch_rho_high2<7, OutT>(tmp, rho, n, st); break;
-    default: launch_rho_high2<8, OutT>(tmp, rho, n, st); break;
+    case 8: launch_rho_high2<8, OutT>(tmp, rho, n, st); break;
+    default: launch_rho_high2<9, OutT>(tmp, rho, n, st); break;   // n = 15 (streamed estimates)
   }
 }
 
 
-// Step (i) into `final_out` (coef or T) with final mode `fm`.
-lre_status run_step1(lre_ctx* ctx, const Plan& P, const uint16_t* counts, uint64_t shots,
-                     const uint32_t* nb_in, void* final_out, Out fm, char* ws, hipStream_t st,
-                     bool mfma) {
-  const int n = P.n;
-  const int64_t nbases = ipow3(n);
+// Per-basis totals N_b of `nbases` rows of 2^lrow counts: the caller's nb_in, else the
+// row sums into nb_ws; their reciprocals into inv.  Returns the totals to use.
+const uint32_t* prepare_totals(int64_t nbases, int lrow, const uint16_t* counts, const uint32_t* nb_in,
+                               uint32_t* nb_ws, double* inv, hipStream_t st) {
   const uint32_t* nb = nb_in;
-  if (P.per_basis && !nb) {
-    uint32_t* nbd = reinterpret_cast<uint32_t*>(ws + P.off_nb);
-    hipLaunchKernelGGL(row_totals_kernel, dim3((unsigned)nbases), dim3(256), 0, st, counts, n, nbd);
-    nb = nbd;
+  if (!nb) {
+    hipLaunchKernelGGL(row_totals_kernel, dim3((unsigned)nbases), dim3(256), 0, st, counts, lrow, nb_ws);
+    nb = nb_ws;
   }
-  uint32_t* rowpart = reinterpret_cast<uint32_t*>(ws + P.off_rowpart);
-  double* inv = nullptr;
-  if (P.per_basis) {
-    inv = reinterpret_cast<double*>(ws + P.off_inv);
-    hipLaunchKernelGGL(reciprocal_kernel, dim3((unsigned)((nbases + 255) / 256)), dim3(256), 0, st, nb, inv, nbases);
-  }
+  hipLaunchKernelGGL(reciprocal_kernel, dim3((unsigned)((nbases + 255) / 256)), dim3(256), 0, st, nb, inv, nbases);
+  return nb;
+}
 
-  Fold1Args a1{counts, n, P.chunks, nb, inv, nullptr, rowpart, shots, P.blocks1, st};
+// The passes of step (i) over 3^n rows of 2^n counts read with row stride 2^lrow: the
+// counts pass (row-sum parts into rowpart) and the later passes, into `final_out` with
+// final mode `fm`.  Per-basis mode reads nb (MFMA form) or inv (plain form).
+lre_status run_passes(lre_ctx* ctx, const Plan& P, const uint16_t* counts, int lrow, uint64_t shots,
+                      const uint32_t* nb, const double* inv, uint32_t* rowpart, void* final_out, Out fm, char* ws,
+                      hipStream_t st, bool mfma) {
+  const int n = P.n;
+  Fold1Args a1{counts, n, P.chunks, lrow, nb, inv, nullptr, rowpart, shots, P.blocks1, st};
   const bool single = P.npass == 0;
   a1.out = single ? final_out : (void*)(ws + P.off_a);
   const bool ok = (mfma && P.q1 == 7) ? fold1_mfma(P.t1, P.per_basis, single ? fm : Out::Partial, a1)
@@ -439,6 +445,24 @@ lre_status run_step1(lre_ctx* ctx, const Plan& P, const uint16_t* counts, uint64
     l += P.F[k];
     tin = P.tout[k];
   }
+  return LRE_OK;
+}
+
+// Step (i) into `final_out` (coef or T) with final mode `fm`.
+lre_status run_step1(lre_ctx* ctx, const Plan& P, const uint16_t* counts, uint64_t shots,
+                     const uint32_t* nb_in, void* final_out, Out fm, char* ws, hipStream_t st,
+                     bool mfma) {
+  const int n = P.n;
+  const int64_t nbases = ipow3(n);
+  const uint32_t* nb = nb_in;
+  double* inv = nullptr;
+  if (P.per_basis) {
+    inv = reinterpret_cast<double*>(ws + P.off_inv);
+    nb = prepare_totals(nbases, n, counts, nb_in, reinterpret_cast<uint32_t*>(ws + P.off_nb), inv, st);
+  }
+  uint32_t* rowpart = reinterpret_cast<uint32_t*>(ws + P.off_rowpart);
+  const lre_status s = run_passes(ctx, P, counts, n, shots, nb, inv, rowpart, final_out, fm, ws, st, mfma);
+  if (s != LRE_OK) return s;
 
   const int64_t rows = ipow3(P.q1);
   const int64_t runs = ((int64_t)1 << (n - P.q1)) / P.chunks;
@@ -446,6 +470,39 @@ lre_status run_step1(lre_ctx* ctx, const Plan& P, const uint16_t* counts, uint64
                      (const uint32_t*)rowpart, rows, runs, nb, P.per_basis ? (uint64_t)0 : shots, nbases,
                      ctx->flags);
   return hipGetLastError() == hipSuccess ? LRE_OK : LRE_E_HIP;
+}
+
+// Steps (i) and (ii) of one instance into caller-given workspace (lre_estimate).
+lre_status estimate_impl(lre_ctx* ctx, int n, const uint16_t* counts, uint64_t shots,
+                         const uint32_t* n_per_basis, double* coef, void* rho, void* workspace,
+                         size_t workspace_bytes, uint32_t flags, void* stream) {
+  if (!ctx || !counts || !coef || n < 1 || n > LRE_MAX_QUBITS) return LRE_E_ARG;
+  if (flags & ~(LRE_NO_RHO | LRE_RHO_FP32 | LRE_WHT_MFMA)) return LRE_E_ARG;
+  if (!aligned(counts, 16) || !aligned(coef, 8)) return LRE_E_ARG;
+  const bool want_rho = !(flags & LRE_NO_RHO);
+  if (want_rho && (!rho || !aligned(rho, 16))) return LRE_E_ARG;
+  Plan P;
+  if (!make_plan(n, shots, flags, P)) return LRE_E_ARG;
+  if (P.total && (!workspace || !aligned(workspace, 256))) return LRE_E_ARG;
+  if (workspace_bytes < P.total) return LRE_E_WORKSPACE;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return LRE_E_HIP;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+
+  record_stage(ctx, 0, st);
+  lre_status s = run_step1(ctx, P, counts, shots, n_per_basis, coef,
+                           P.per_basis ? Out::CoefPerBasis : Out::CoefUniform, ws, st,
+                           (flags & LRE_WHT_MFMA) != 0);
+  if (s != LRE_OK) return s;
+  record_stage(ctx, 2, st);
+  if (want_rho) {
+    if (flags & LRE_RHO_FP32) launch_rho<float>(P, coef, rho, ws, st);
+    else launch_rho<double>(P, coef, rho, ws, st);
+    if (hipGetLastError() != hipSuccess) return LRE_E_HIP;
+  }
+  record_stage(ctx, 3, st);
+  return LRE_OK;
 }
 
 }  // namespace
@@ -501,33 +558,8 @@ size_t lre_workspace_bytes(int n, uint64_t shots, uint32_t flags) {
 lre_status lre_estimate(lre_ctx* ctx, int n, const uint16_t* counts, uint64_t shots,
                         const uint32_t* n_per_basis, double* coef, void* rho, void* workspace,
                         size_t workspace_bytes, uint32_t flags, void* stream) {
-  if (!ctx || !counts || !coef || n < 1 || n > LRE_MAX_QUBITS) return LRE_E_ARG;
-  if (flags & ~(LRE_NO_RHO | LRE_RHO_FP32 | LRE_WHT_MFMA)) return LRE_E_ARG;
-  if (!aligned(counts, 16) || !aligned(coef, 8)) return LRE_E_ARG;
-  const bool want_rho = !(flags & LRE_NO_RHO);
-  if (want_rho && (!rho || !aligned(rho, 16))) return LRE_E_ARG;
-  Plan P;
-  if (!make_plan(n, shots, flags, P)) return LRE_E_ARG;
-  if (P.total && (!workspace || !aligned(workspace, 256))) return LRE_E_ARG;
-  if (workspace_bytes < P.total) return LRE_E_WORKSPACE;
-  DeviceGuard g(ctx->device);
-  if (!g.ok) return LRE_E_HIP;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  char* ws = static_cast<char*>(workspace);
-
-  record_stage(ctx, 0, st);
-  lre_status s = run_step1(ctx, P, counts, shots, n_per_basis, coef,
-                           P.per_basis ? Out::CoefPerBasis : Out::CoefUniform, ws, st,
-                           (flags & LRE_WHT_MFMA) != 0);
-  if (s != LRE_OK) return s;
-  record_stage(ctx, 2, st);
-  if (want_rho) {
-    if (flags & LRE_RHO_FP32) launch_rho<float>(P, coef, rho, ws, st);
-    else launch_rho<double>(P, coef, rho, ws, st);
-    if (hipGetLastError() != hipSuccess) return LRE_E_HIP;
-  }
-  record_stage(ctx, 3, st);
-  return LRE_OK;
+  return estimate_impl(ctx, n, counts, shots, n_per_basis, coef, rho, workspace, workspace_bytes, flags,
+                       stream);
 }
 
 lre_status lre_set_stage_events(lre_ctx* ctx, void* const* events, int count) {
@@ -597,6 +629,343 @@ lre_status lre_signed_sums(lre_ctx* ctx, int n, const uint16_t* counts, const in
 #undef LRE_SS
   }
   return hipGetLastError() == hipSuccess ? LRE_OK : LRE_E_HIP;
+}
+
+
+// ---------------------------------------------------------------------------------
+// Streamed estimation (lre_stream_*): slabs of 3^(n-h) consecutive bases, each cut
+// into 2^h outcome segments run as (n-h)-qubit instances, the top h qubits folded into
+// the caller's coefficient array, which accumulates until lre_stream_finish.
+
+}  // extern "C"
+
+struct lre_stream {
+  lre_ctx* ctx = nullptr;
+  int n = 0, h = 0, np = 0;
+  uint64_t shots = 0;
+  uint32_t flags = 0;
+  Plan P;                     // plan of one (n-h)-qubit segment (no rho), final sums raw
+  Ty tV = Ty::F64;            // type of the segments' final sums
+  int64_t slabs = 0;          // 3^h
+  std::vector<uint8_t> pushed;
+  int64_t npushed = 0;
+  double* coef = nullptr;     // accumulator / output, set by lre_stream_begin
+  size_t off_seg = 0, off_V = 0, off_rowpart = 0, off_stage = 0, off_tmp = 0, total = 0;
+  size_t seg_rowpart = 0;     // bytes of one segment's row-sum parts
+  size_t stage_bytes = 0;
+  hipEvent_t copied = nullptr;
+};
+
+namespace {
+
+lre_status stream_ws_check(const lre_stream* S, void* ws, size_t ws_bytes) {
+  if (!ws || !aligned(ws, 256)) return LRE_E_ARG;
+  if (ws_bytes < S->total) return LRE_E_WORKSPACE;
+  return LRE_OK;
+}
+
+template <int H>
+void launch_top_fold(const lre_stream* S, const void* V, uint32_t atop, hipStream_t st) {
+  const int64_t ncols = ipow4(S->np);
+  const dim3 grid((unsigned)((ncols + 255) / 256));
+  if (S->tV == Ty::U32)
+    hipLaunchKernelGGL((stream_top_fold_kernel<H, uint32_t>), grid, dim3(256), 0, st, (const uint32_t*)V, S->coef,
+                       ncols, atop);
+  else
+    hipLaunchKernelGGL((stream_top_fold_kernel<H, double>), grid, dim3(256), 0, st, (const double*)V, S->coef,
+                       ncols, atop);
+}
+
+// One slab already in device memory: totals, the 2^h segments, the row check, the fold
+// of the top qubits into the accumulator.
+lre_status stream_slab(lre_stream* S, int64_t slab, const uint16_t* counts, const uint32_t* nb_in, char* ws,
+                       hipStream_t st) {
+  const Plan& P = S->P;
+  const int np = S->np, n = S->n, h = S->h;
+  const int64_t nbases = ipow3(np);
+  char* seg_ws = ws + S->off_seg;
+  const uint32_t* nb = nb_in;
+  double* inv = nullptr;
+  if (P.per_basis) {
+    inv = reinterpret_cast<double*>(seg_ws + P.off_inv);
+    nb = prepare_totals(nbases, n, counts, nb_in, reinterpret_cast<uint32_t*>(seg_ws + P.off_nb), inv, st);
+  }
+  const size_t vbytes = (size_t)ipow4(np) * ty_size(S->tV);
+  for (int sg = 0; sg < (1 << h); ++sg) {
+    uint32_t* rowpart = reinterpret_cast<uint32_t*>(ws + S->off_rowpart + (size_t)sg * S->seg_rowpart);
+    void* V = ws + S->off_V + (size_t)sg * vbytes;
+    const lre_status s = run_passes(S->ctx, P, counts + ((int64_t)sg << np), n, S->shots, nb, inv, rowpart, V,
+                                    Out::Partial, seg_ws, st, (S->flags & LRE_WHT_MFMA) != 0);
+    if (s != LRE_OK) return s;
+  }
+  const int64_t rows = ipow3(P.q1);
+  const int64_t runs = ((int64_t)1 << (np - P.q1)) / P.chunks;
+  hipLaunchKernelGGL(check_rows_seg_kernel, dim3((unsigned)((nbases + 255) / 256)), dim3(256), 0, st,
+                     (const uint32_t*)(ws + S->off_rowpart), (int64_t)(S->seg_rowpart / 4), 1 << h, rows, runs, nb,
+                     P.per_basis ? (uint64_t)0 : S->shots, nbases, S->ctx->flags);
+  // Letters of the top qubits: digit p of the slab index (base 3) is qubit h - p.
+  uint32_t atop = 0;
+  int64_t t = slab;
+  for (int p = 0; p < h; ++p) {
+    atop |= (uint32_t)(t % 3 + 1) << (2 * p);
+    t /= 3;
+  }
+  const void* V = ws + S->off_V;
+  switch (h) {
+    case 1: launch_top_fold<1>(S, V, atop, st); break;
+    case 2: launch_top_fold<2>(S, V, atop, st); break;
+    case 3: launch_top_fold<3>(S, V, atop, st); break;
+    case 4: launch_top_fold<4>(S, V, atop, st); break;
+    case 5: launch_top_fold<5>(S, V, atop, st); break;
+    default: launch_top_fold<6>(S, V, atop, st); break;
+  }
+  return hipGetLastError() == hipSuccess ? LRE_OK : LRE_E_HIP;
+}
+
+lre_status stream_take_slab(lre_stream* S, int64_t slab) {
+  if (!S->coef) return LRE_E_ARG;                       // lre_stream_begin first
+  if (slab < 0 || slab >= S->slabs || S->pushed[(size_t)slab]) return LRE_E_ARG;
+  S->pushed[(size_t)slab] = 1;
+  ++S->npushed;
+  return LRE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lre_status lre_stream_create(lre_ctx* ctx, int n, int h, uint64_t shots, uint32_t flags, lre_stream** out) {
+  if (!out) return LRE_E_ARG;
+  *out = nullptr;
+  if (!ctx || n > LRE_STREAM_MAX_QUBITS || h < 1 || h > 6 || n - h < 8 || n - h > LRE_MAX_QUBITS)
+    return LRE_E_ARG;
+  if (flags & ~(LRE_NO_RHO | LRE_RHO_FP32 | LRE_WHT_MFMA | LRE_STREAM_HOST)) return LRE_E_ARG;
+  lre_stream* S = new (std::nothrow) lre_stream;
+  if (!S) return LRE_E_HIP;
+  S->ctx = ctx;
+  S->n = n;
+  S->h = h;
+  S->np = n - h;
+  S->shots = shots;
+  S->flags = flags;
+  if (!make_plan(S->np, shots, (flags & LRE_WHT_MFMA) | LRE_NO_RHO, S->P)) {
+    delete S;
+    return LRE_E_ARG;
+  }
+  S->tV = S->P.npass ? S->P.tout[S->P.npass - 1] : S->P.t1;
+  S->slabs = ipow3(h);
+  S->pushed.assign((size_t)S->slabs, 0);
+  const size_t segs = (size_t)1 << h;
+  S->seg_rowpart = align256((size_t)S->P.blocks1 * (size_t)ipow3(S->P.q1) * 4);
+  size_t off = 0;
+  S->off_seg = off; off += align256(S->P.total);
+  S->off_V = off; off += align256(segs * (size_t)ipow4(S->np) * ty_size(S->tV));
+  S->off_rowpart = off; off += segs * S->seg_rowpart;
+  S->stage_bytes = (size_t)ipow3(S->np) << n;
+  S->stage_bytes *= 2;
+  if (flags & LRE_STREAM_HOST) {
+    S->off_stage = off;
+    off += align256(S->stage_bytes);
+    off += align256(S->P.per_basis ? (size_t)ipow3(S->np) * 4 : 0);   // staged N_b
+  }
+  // step (ii)'s intermediate reuses the (then dead) segment buffers
+  const size_t tmp = (flags & LRE_NO_RHO) ? 0 : (size_t)ipow4(n) * 16;
+  S->off_tmp = 0;
+  S->total = off > tmp ? off : tmp;
+  DeviceGuard g(ctx->device);
+  if (!g.ok || hipEventCreateWithFlags(&S->copied, hipEventDisableTiming) != hipSuccess) {
+    delete S;
+    return LRE_E_HIP;
+  }
+  *out = S;
+  return LRE_OK;
+}
+
+size_t lre_stream_workspace_bytes(const lre_stream* S) { return S ? S->total : 0; }
+
+lre_status lre_stream_begin(lre_stream* S, double* coef, void* workspace, size_t workspace_bytes, void* stream) {
+  if (!S || !coef || !aligned(coef, 8)) return LRE_E_ARG;
+  const lre_status c = stream_ws_check(S, workspace, workspace_bytes);
+  if (c != LRE_OK) return c;
+  DeviceGuard g(S->ctx->device);
+  if (!g.ok) return LRE_E_HIP;
+  S->coef = coef;
+  std::fill(S->pushed.begin(), S->pushed.end(), 0);
+  S->npushed = 0;
+  // the accumulator starts at zero (a fill kernel: capturable, no memset node)
+  const int64_t words = ipow4(S->n) * 2;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((words + 255) / 256)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), reinterpret_cast<uint32_t*>(coef), words, 0u);
+  return hipGetLastError() == hipSuccess ? LRE_OK : LRE_E_HIP;
+}
+
+lre_status lre_stream_push(lre_stream* S, int64_t slab, const uint16_t* counts, const uint32_t* n_per_basis,
+                           void* workspace, size_t workspace_bytes, void* stream) {
+  if (!S || !counts || !aligned(counts, 16)) return LRE_E_ARG;
+  if (n_per_basis && !aligned(n_per_basis, 4)) return LRE_E_ARG;
+  lre_status c = stream_ws_check(S, workspace, workspace_bytes);
+  if (c != LRE_OK) return c;
+  if ((c = stream_take_slab(S, slab)) != LRE_OK) return c;
+  DeviceGuard g(S->ctx->device);
+  if (!g.ok) return LRE_E_HIP;
+  return stream_slab(S, slab, counts, S->P.per_basis ? n_per_basis : nullptr, static_cast<char*>(workspace),
+                     static_cast<hipStream_t>(stream));
+}
+
+lre_status lre_stream_push_host(lre_stream* S, int64_t slab, const uint16_t* counts, const uint32_t* n_per_basis,
+                                void* workspace, size_t workspace_bytes, void* stream) {
+  if (!S || !counts) return LRE_E_ARG;
+  if (!(S->flags & LRE_STREAM_HOST)) return LRE_E_ARG;
+  lre_status c = stream_ws_check(S, workspace, workspace_bytes);
+  if (c != LRE_OK) return c;
+  if (slab < 0 || slab >= S->slabs || S->pushed[(size_t)slab] || !S->coef) return LRE_E_ARG;
+  DeviceGuard g(S->ctx->device);
+  if (!g.ok) return LRE_E_HIP;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  uint16_t* stage = reinterpret_cast<uint16_t*>(ws + S->off_stage);
+  uint32_t* nb_stage = nullptr;
+  // The staging buffer is reused by every slab: the copy is ordered after the previous
+  // slab's kernels on the same stream.
+  if (hipMemcpyAsync(stage, counts, S->stage_bytes, hipMemcpyHostToDevice, st) != hipSuccess) return LRE_E_HIP;
+  if (S->P.per_basis && n_per_basis) {
+    nb_stage = reinterpret_cast<uint32_t*>(ws + S->off_stage + align256(S->stage_bytes));
+    if (hipMemcpyAsync(nb_stage, n_per_basis, (size_t)ipow3(S->np) * 4, hipMemcpyHostToDevice, st) != hipSuccess)
+      return LRE_E_HIP;
+  }
+  if (hipEventRecord(S->copied, st) != hipSuccess) return LRE_E_HIP;
+  if ((c = stream_take_slab(S, slab)) != LRE_OK) return c;
+  c = stream_slab(S, slab, stage, nb_stage, ws, st);
+  if (c != LRE_OK) return c;
+  // the caller may reuse its host buffers once the copies are done (the slab's kernels
+  // keep running)
+  return hipEventSynchronize(S->copied) == hipSuccess ? LRE_OK : LRE_E_HIP;
+}
+
+lre_status lre_stream_finish(lre_stream* S, void* rho, void* workspace, size_t workspace_bytes, void* stream) {
+  if (!S || !S->coef) return LRE_E_ARG;
+  if (S->npushed != S->slabs) return LRE_E_ARG;
+  const bool want_rho = !(S->flags & LRE_NO_RHO);
+  if (want_rho && (!rho || !aligned(rho, 16))) return LRE_E_ARG;
+  const lre_status c = stream_ws_check(S, workspace, workspace_bytes);
+  if (c != LRE_OK) return c;
+  DeviceGuard g(S->ctx->device);
+  if (!g.ok) return LRE_E_HIP;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t count = ipow4(S->n);
+  hipLaunchKernelGGL(stream_finish_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, S->coef, S->n,
+                     S->P.per_basis ? (uint64_t)0 : S->shots, count);
+  if (hipGetLastError() != hipSuccess) return LRE_E_HIP;
+  if (want_rho) {
+    Plan R;
+    R.n = S->n;
+    R.off_tmp = S->off_tmp;
+    if (S->flags & LRE_RHO_FP32) launch_rho<float>(R, S->coef, rho, static_cast<char*>(workspace), st);
+    else launch_rho<double>(R, S->coef, rho, static_cast<char*>(workspace), st);
+    if (hipGetLastError() != hipSuccess) return LRE_E_HIP;
+  }
+  S->coef = nullptr;
+  return LRE_OK;
+}
+
+void lre_stream_destroy(lre_stream* S) {
+  if (!S) return;
+  {
+    DeviceGuard g(S->ctx->device);
+    if (S->copied) (void)hipEventDestroy(S->copied);
+  }
+  delete S;
+}
+
+
+// ---------------------------------------------------------------------------------
+// Reduced measurement set (Sec. VI): 4^n product operators of one informationally
+// complete 4-operator set per qubit.
+
+size_t lre_povm_workspace_bytes(int n, uint32_t flags) {
+  if (n < 1 || n > LRE_MAX_QUBITS) return 0;
+  const size_t head = 256;   // M (16 binary64) and the 64-bit total N
+  const size_t tmp = (!(flags & LRE_NO_RHO) && n > kRhoJ) ? (size_t)ipow4(n) * 16 : 0;
+  return head + align256(tmp);
+}
+
+lre_status lre_povm_estimate(lre_ctx* ctx, int n, const uint16_t* counts, const double* G, double* coef, void* rho,
+                             void* workspace, size_t workspace_bytes, uint32_t flags, void* stream) {
+  if (!ctx || !counts || !G || !coef || n < 1 || n > LRE_MAX_QUBITS) return LRE_E_ARG;
+  if (flags & ~(LRE_NO_RHO | LRE_RHO_FP32)) return LRE_E_ARG;
+  if (!aligned(counts, 16) || !aligned(G, 8) || !aligned(coef, 8)) return LRE_E_ARG;
+  const bool want_rho = !(flags & LRE_NO_RHO);
+  if (want_rho && (!rho || !aligned(rho, 16))) return LRE_E_ARG;
+  const size_t need = lre_povm_workspace_bytes(n, flags);
+  if (!workspace || !aligned(workspace, 256)) return LRE_E_ARG;
+  if (workspace_bytes < need) return LRE_E_WORKSPACE;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return LRE_E_HIP;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  double* M = reinterpret_cast<double*>(ws);
+  unsigned long long* total = reinterpret_cast<unsigned long long*>(ws + 128);
+  const int64_t count = ipow4(n);
+
+  record_stage(ctx, 0, st);
+  hipLaunchKernelGGL(povm_setup_kernel, dim3(1), dim3(64), 0, st, G, M, total, ctx->flags);
+  const int64_t tb = std::min<int64_t>((count + 255) / 256, 4096);
+  hipLaunchKernelGGL(povm_total_kernel, dim3((unsigned)tb), dim3(256), 0, st, counts, count, total);
+  hipLaunchKernelGGL(povm_check_kernel, dim3(1), dim3(64), 0, st, (const unsigned long long*)total, ctx->flags);
+  record_stage(ctx, 1, st);
+
+  // passes: the lowest min(n, 6) digits in one LDS tile, then 4 digits at a time in LDS,
+  // then the remaining 1..3 in registers; the last pass divides by N
+  const int J = n < 6 ? n : 6;
+  const int64_t tiles = count >> (2 * J);
+  const bool only = J == n;
+  switch (J) {
+#define LRE_POVM_LOW(JJ)                                                                                   \
+  case JJ:                                                                                                 \
+    if (only)                                                                                              \
+      hipLaunchKernelGGL((povm_low_kernel<JJ, true>), dim3((unsigned)tiles), dim3(256), 0, st, counts, coef, \
+                         (const double*)M, (const unsigned long long*)total);                              \
+    else                                                                                                   \
+      hipLaunchKernelGGL((povm_low_kernel<JJ, false>), dim3((unsigned)tiles), dim3(256), 0, st, counts, coef, \
+                         (const double*)M, (const unsigned long long*)total);                              \
+    break;
+    LRE_POVM_LOW(1) LRE_POVM_LOW(2) LRE_POVM_LOW(3) LRE_POVM_LOW(4) LRE_POVM_LOW(5) LRE_POVM_LOW(6)
+#undef LRE_POVM_LOW
+  }
+  int lo = J;
+  while (n - lo >= 4) {
+    const bool last = n - lo == 4;
+    const int64_t blocks = (count >> 8) / kPovmCols;
+    if (last)
+      hipLaunchKernelGGL((povm_high4_kernel<true>), dim3((unsigned)blocks), dim3(256), 0, st, coef, n, lo,
+                         (const double*)M, (const unsigned long long*)total);
+    else
+      hipLaunchKernelGGL((povm_high4_kernel<false>), dim3((unsigned)blocks), dim3(256), 0, st, coef, n, lo,
+                         (const double*)M, (const unsigned long long*)total);
+    lo += 4;
+  }
+  if (n > lo) {
+    const int F = n - lo;
+    const int64_t cols = count >> (2 * F);
+    const dim3 grid((unsigned)((cols + 255) / 256));
+    switch (F) {
+      case 1: hipLaunchKernelGGL((povm_reg_kernel<1, true>), grid, dim3(256), 0, st, coef, n, lo, (const double*)M, (const unsigned long long*)total); break;
+      case 2: hipLaunchKernelGGL((povm_reg_kernel<2, true>), grid, dim3(256), 0, st, coef, n, lo, (const double*)M, (const unsigned long long*)total); break;
+      default: hipLaunchKernelGGL((povm_reg_kernel<3, true>), grid, dim3(256), 0, st, coef, n, lo, (const double*)M, (const unsigned long long*)total); break;
+    }
+  }
+  if (hipGetLastError() != hipSuccess) return LRE_E_HIP;
+  record_stage(ctx, 2, st);
+  if (want_rho) {
+    Plan R;
+    R.n = n;
+    R.off_tmp = 256;
+    if (flags & LRE_RHO_FP32) launch_rho<float>(R, coef, rho, ws, st);
+    else launch_rho<double>(R, coef, rho, ws, st);
+    if (hipGetLastError() != hipSuccess) return LRE_E_HIP;
+  }
+  record_stage(ctx, 3, st);
+  return LRE_OK;
 }
 
 }  // extern "C"

@@ -38,9 +38,9 @@ constexpr int kQ = 7;             // counts-pass tile qubits (n >= 7)
 constexpr int kJ = 6;             // low step-(ii) qubits (n > 6)
 constexpr uint32_t kWaitLimit = 1u << 24;  // sleeps of ~64 clocks before a wait gives up
 
-enum Kind : uint8_t { K_SMALL = 0, K_COUNTS = 1, K_FOLD = 3, K_RHO = 4 };
-// variant bits
-enum : uint8_t { V_MAD24 = 16, V_FP32 = 32, V_RHO = 64 };
+enum Kind : uint8_t { K_SMALL = 0, K_COUNTS = 1, K_TOTALS = 2, K_FOLD = 3, K_RHO = 4 };
+// variant bits (V_PB: the instance has per-basis totals, binary64 sums)
+enum : uint8_t { V_MAD24 = 16, V_FP32 = 32, V_RHO = 64, V_PB = 128 };
 
 struct BItem {
   int32_t inst;
@@ -56,8 +56,10 @@ struct BInst {
   const uint16_t* counts;
   double* coef;
   void* rho;
-  uint64_t shots;
+  const uint32_t* nb_in;      // caller's per-basis totals (per-basis mode) or NULL
+  uint64_t shots;             // 0: per-basis totals
   int64_t off_part, off_tmp;  // workspace offsets
+  int64_t off_nb, off_inv;    // per-basis mode: N_b and 1/N_b in the workspace
   int32_t n, q1;
 };
 
@@ -71,8 +73,10 @@ struct BInstG {
   const LRE_GLOBAL uint16_t* counts;
   LRE_GLOBAL double* coef;
   LRE_GLOBAL char* rho;
+  const LRE_GLOBAL uint32_t* nb_in;
   uint64_t shots;
   int64_t off_part, off_tmp;
+  int64_t off_nb, off_inv;
   int32_t n, q1;
 };
 
@@ -81,9 +85,12 @@ __device__ __forceinline__ BInstG global_view(const BInst& I) {
   G.counts = (const LRE_GLOBAL uint16_t*)I.counts;
   G.coef = (LRE_GLOBAL double*)I.coef;
   G.rho = (LRE_GLOBAL char*)I.rho;
+  G.nb_in = (const LRE_GLOBAL uint32_t*)I.nb_in;
   G.shots = I.shots;
   G.off_part = I.off_part;
   G.off_tmp = I.off_tmp;
+  G.off_nb = I.off_nb;
+  G.off_inv = I.off_inv;
   G.n = I.n;
   G.q1 = I.q1;
   return G;
@@ -93,6 +100,9 @@ constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
 constexpr size_t kLdsCounts = (size_t)StreamGeom<kQ>::NACC * 4 + (size_t)StreamGeom<kQ>::NROWS * 4;
 constexpr size_t kLdsRhoLow = 2 * (size_t)RhoLowLds<kJ>::SIZE * 8;
 constexpr size_t kLds = cmax(kLdsCounts, kLdsRhoLow);
+// per-basis plans: binary64 accumulators (one workgroup per CU)
+constexpr size_t kLdsCountsPB = (size_t)StreamGeom<kQ>::NACC * 8 + (size_t)StreamGeom<kQ>::NROWS * 4;
+constexpr size_t kLdsPB = cmax(kLdsCountsPB, kLdsRhoLow);
 constexpr int64_t kRhoElemsPerBlock = 4096;  // step-(ii) high elements per unit of rho_blocks
 
 // The callees below take the instance with global-typed pointers; the generic pointers
@@ -148,6 +158,74 @@ __device__ __noinline__ void run_small(const BInstG& I, uint8_t var, int tid, LR
   }
 }
 
+// Per-basis totals of bases [b0, b1) (Sec. II eq. 3 frequencies p = c / N_b): N_b, the
+// caller's or else the row sum, into the workspace, 1/N_b (correctly rounded) beside
+// it, FLAG_EMPTY for an empty basis.  A group of 16 lanes per basis row.
+__device__ __noinline__ void run_totals(const BInstG& I, int64_t b0, int64_t b1, int tid, LRE_GLOBAL char* ws,
+                                        uint32_t* flags) {
+  LRE_GLOBAL uint32_t* nb = (LRE_GLOBAL uint32_t*)(ws + I.off_nb);
+  LRE_GLOBAL double* inv = (LRE_GLOBAL double*)(ws + I.off_inv);
+  constexpr int kGroups = kBT / 16;
+  const int grp = tid / 16, lam = tid % 16;
+  const int64_t d = (int64_t)1 << I.n;
+  for (int64_t b = b0 + grp; b < b1; b += kGroups) {   // uniform within a group
+    uint32_t N;
+    if (I.nb_in) {
+      N = I.nb_in[b];
+    } else {
+      uint32_t sum = 0;
+      for (int64_t o = lam; o < d; o += 16) sum += I.counts[b * d + o];
+#pragma unroll
+      for (int o = 8; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 16);
+      N = sum;
+    }
+    if (lam == 0) {
+      nb[b] = N;
+      inv[b] = N ? 1.0 / (double)N : 0.0;
+      if (!N) atomicOr(flags, (uint32_t)FLAG_EMPTY);
+    }
+  }
+}
+
+// A per-basis instance with n <= 7 in one workgroup: totals, counts pass with binary64
+// accumulators (row totals checked against N_b), step (ii).
+template <int Q, bool PREFETCH>
+__device__ __noinline__ void run_small_pb(const BInstG& I, uint8_t var, int tid, LRE_GLOBAL char* ws, char* smem,
+                                          uint32_t* flags) {
+  run_totals(I, 0, ipow3(I.n), tid, ws, flags);
+  __syncthreads();  // workgroup scope: the totals written above are visible to the block
+  double* acc = reinterpret_cast<double*>(smem);
+  uint32_t* rs = reinterpret_cast<uint32_t*>(acc + StreamGeom<Q>::NACC);
+  counts_block<Q, kBT, double, true, Out::CoefPerBasis, false, PREFETCH>(
+      (const uint16_t*)I.counts, I.n, 1, (const double*)g2p(ws + I.off_inv), (void*)(double*)I.coef, nullptr, 0, 0,
+      tid, acc, rs, flags, (const uint32_t*)g2p(ws + I.off_nb));
+  __syncthreads();
+  if (var & V_RHO) {
+    double* re = reinterpret_cast<double*>(smem);
+    double* im = re + (kLds / 16);
+    if (var & V_FP32) small_rho<Q, float>(I, tid, ws, re, im);
+    else small_rho<Q, double>(I, tid, ws, re, im);
+  }
+}
+
+// Per-basis counts-pass row groups [g0, g1): binary64 partials, rows checked against N_b.
+template <bool PREFETCH>
+__device__ __noinline__ void run_counts_pb(const BInstG& I, int64_t g0, int64_t g1, int tid, LRE_GLOBAL char* ws,
+                                           char* smem, uint32_t* flags) {
+  double* acc = reinterpret_cast<double*>(smem);
+  uint32_t* rs = reinterpret_cast<uint32_t*>(acc + StreamGeom<kQ>::NACC);
+  void* part = (void*)g2p(ws + I.off_part);
+  const double* inv = (const double*)g2p(ws + I.off_inv);
+  const uint32_t* nb = (const uint32_t*)g2p(ws + I.off_nb);
+  const uint16_t* counts = (const uint16_t*)I.counts;
+  const int chunks = 1 << (I.n - kQ);
+  for (int64_t g = g0; g < g1; ++g) {
+    counts_block<kQ, kBT, double, true, Out::Partial, false, PREFETCH>(counts, I.n, chunks, inv, part, nullptr, 0, g,
+                                                                      tid, acc, rs, flags, nb);
+    __syncthreads();
+  }
+}
+
 // Row groups [g0, g1) (3^7 rows each): one block call per group covering all 2^(n-7)
 // outcome tiles of its rows, so the row totals are complete and checked in the block.
 template <bool MAD24, bool PREFETCH>
@@ -169,12 +247,12 @@ __device__ __noinline__ void run_counts(const BInstG& I, int64_t g0, int64_t g1,
 // 6^F inputs of C columns into registers, then folds them.  (Folding straight from
 // memory serialises the columns: the next column's loads cannot pass this column's
 // coefficient stores, and the loads' wait covers the stores.)
-template <int F>
-__device__ __forceinline__ void fold_cols(const uint32_t* in, double* coef, int n, uint64_t shots, int64_t c0,
+template <int F, typename Tin, Out MODE>
+__device__ __forceinline__ void fold_cols(const Tin* in, double* coef, int n, uint64_t shots, int64_t c0,
                                           int64_t c1, int tid) {
   constexpr int NIN = (int)ipow3(F) << F, C = 4;
   for (int64_t base = c0 + tid; base < c1; base += (int64_t)kBT * C) {
-    uint32_t x[C][NIN];
+    Tin x[C][NIN];
 #pragma unroll
     for (int j = 0; j < C; ++j) {
       const int64_t col = base + (int64_t)j * kBT;
@@ -189,7 +267,7 @@ __device__ __forceinline__ void fold_cols(const uint32_t* in, double* coef, int 
     for (int j = 0; j < C; ++j) {
       const int64_t col = base + (int64_t)j * kBT;
       if (col < c1)
-        fold_partial_col_src<F, uint32_t, uint32_t, Out::CoefUniform>(
+        fold_partial_col_src<F, Tin, Tin, MODE>(
             [&](int beta, int sg) __attribute__((always_inline)) { return x[j][beta * (1 << F) + sg]; }, coef,
             n, F, kQ, shots, col);
     }
@@ -200,8 +278,16 @@ __device__ __noinline__ void run_fold(const BInstG& I, int64_t c0, int64_t c1, i
   const uint32_t* in = reinterpret_cast<const uint32_t*>(g2p(ws + I.off_part));
   double* coef = (double*)I.coef;
   const int h = I.n - kQ;
-  if (h == 1) fold_cols<1>(in, coef, I.n, I.shots, c0, c1, tid);
-  else fold_cols<2>(in, coef, I.n, I.shots, c0, c1, tid);
+  if (h == 1) fold_cols<1, uint32_t, Out::CoefUniform>(in, coef, I.n, I.shots, c0, c1, tid);
+  else fold_cols<2, uint32_t, Out::CoefUniform>(in, coef, I.n, I.shots, c0, c1, tid);
+}
+
+__device__ __noinline__ void run_fold_pb(const BInstG& I, int64_t c0, int64_t c1, int tid, LRE_GLOBAL char* ws) {
+  const double* in = reinterpret_cast<const double*>(g2p(ws + I.off_part));
+  double* coef = (double*)I.coef;
+  const int h = I.n - kQ;
+  if (h == 1) fold_cols<1, double, Out::CoefPerBasis>(in, coef, I.n, 0, c0, c1, tid);
+  else fold_cols<2, double, Out::CoefPerBasis>(in, coef, I.n, 0, c0, c1, tid);
 }
 
 // Step (ii) for the x_hi values [x0, x1) of an instance with n > 7: the low transform of
@@ -248,19 +334,40 @@ __device__ __forceinline__ void dispatch_small(const BInstG& I, uint8_t var, int
   }
 }
 
-// ctl[0]: next item; ctl[1 + 3 j + k]: completion counter of stage k of instance j.
+template <bool PREFETCH>
+__device__ __forceinline__ void dispatch_small_pb(const BInstG& I, uint8_t var, int tid, LRE_GLOBAL char* ws,
+                                                  char* smem, uint32_t* flags) {
+  switch (I.n) {
+    case 1: run_small_pb<1, PREFETCH>(I, var, tid, ws, smem, flags); break;
+    case 2: run_small_pb<2, PREFETCH>(I, var, tid, ws, smem, flags); break;
+    case 3: run_small_pb<3, PREFETCH>(I, var, tid, ws, smem, flags); break;
+    case 4: run_small_pb<4, PREFETCH>(I, var, tid, ws, smem, flags); break;
+    case 5: run_small_pb<5, PREFETCH>(I, var, tid, ws, smem, flags); break;
+    case 6: run_small_pb<6, PREFETCH>(I, var, tid, ws, smem, flags); break;
+    default: run_small_pb<7, PREFETCH>(I, var, tid, ws, smem, flags); break;
+  }
+}
+
+// ctl[0]: next item; ctl[1 + 3 j + k]: completion counter of instance j's counts pass
+// (k = 0), later fold (k = 1) and per-basis totals (k = 2).
 // WORKERS: persistent workgroups per CU the launch is shaped for (one: registers for the
-// row prefetch; two: no prefetch, 128 registers).
-template <int WORKERS>
+// row prefetch; two: no prefetch, 128 registers).  PB: the plan has per-basis instances
+// (binary64 counts-pass accumulators, one workgroup per CU); only then are their item
+// variants compiled in.
+template <int WORKERS, bool PB>
 __global__ __launch_bounds__(kBT, WORKERS == 2 ? 4 : 1) void batch_kernel(
-    const BItem* __restrict__ items, int nitems, const BInst* __restrict__ insts, char* __restrict__ ws_arg,
-    uint32_t* __restrict__ ctl, uint32_t* __restrict__ flags) {
+    const BItem* __restrict__ items, const int* __restrict__ nitems_ptr, const BInst* __restrict__ insts,
+    char* __restrict__ ws_arg, uint32_t* __restrict__ ctl, uint32_t* __restrict__ flags) {
   constexpr bool PF = WORKERS == 1;
-  __shared__ __align__(16) char smem[kLds];
+  static_assert(!PB || WORKERS == 1, "per-basis plans run one workgroup per CU");
+  __shared__ __align__(16) char smem[PB ? kLdsPB : kLds];
   __shared__ int s_item;
   __shared__ int s_skip;
   const int tid = threadIdx.x;
   LRE_GLOBAL char* ws = (LRE_GLOBAL char*)ws_arg;
+  // The item count lives beside the list (not in the launch arguments), so a launch
+  // captured into a graph runs whatever list the plan holds when it is replayed.
+  const int nitems = *nitems_ptr;
   for (;;) {
     if (tid == 0) s_item = (int)atomicAdd(&ctl[0], 1u);
     __syncthreads();
@@ -287,13 +394,39 @@ __global__ __launch_bounds__(kBT, WORKERS == 2 ? 4 : 1) void batch_kernel(
       if (s_skip) continue;  // uniform: the skipped item's counter never moves, its consumers time out too
     }
     const BInstG I = global_view(insts[W.inst]);
+    const bool pb = PB && (W.variant & V_PB);
     switch (W.kind) {
-      case K_SMALL: dispatch_small<PF>(I, W.variant, tid, ws, smem, flags); break;
+      case K_SMALL:
+        if constexpr (PB) {
+          if (pb) {
+            dispatch_small_pb<PF>(I, W.variant, tid, ws, smem, flags);
+            break;
+          }
+        }
+        dispatch_small<PF>(I, W.variant, tid, ws, smem, flags);
+        break;
       case K_COUNTS:
+        if constexpr (PB) {
+          if (pb) {
+            run_counts_pb<PF>(I, W.begin, W.end, tid, ws, smem, flags);
+            break;
+          }
+        }
         if (W.variant & V_MAD24) run_counts<true, PF>(I, W.begin, W.end, tid, ws, smem, flags);
         else run_counts<false, PF>(I, W.begin, W.end, tid, ws, smem, flags);
         break;
-      case K_FOLD: run_fold(I, W.begin, W.end, tid, ws); break;
+      case K_TOTALS:
+        if constexpr (PB) run_totals(I, W.begin, W.end, tid, ws, flags);
+        break;
+      case K_FOLD:
+        if constexpr (PB) {
+          if (pb) {
+            run_fold_pb(I, W.begin, W.end, tid, ws);
+            break;
+          }
+        }
+        run_fold(I, W.begin, W.end, tid, ws);
+        break;
       default:
         if (W.variant & V_FP32) run_rho<float>(I, W.begin, W.end, tid, ws, smem);
         else run_rho<double>(I, W.begin, W.end, tid, ws, smem);
@@ -316,6 +449,7 @@ struct InstMeta {
   int n = 0, q1 = 0, F = 0;     // F: later-pass qubits (n - 7 when n > 7)
   int64_t blocks1 = 0;          // counts-pass tiles
   bool mad24 = false;
+  bool pb = false;              // per-basis totals
   int64_t counts = 0;           // 6^n, the ordering key
 };
 
@@ -329,12 +463,14 @@ struct lre_batch {
   std::vector<BInst> dinst_host;
   lre_batch_tiles tiles{};
   BInst* d_inst = nullptr;
-  BItem* d_items = nullptr;
+  BItem* d_items = nullptr;     // work list, allocated once at the largest list any
+  int* d_nitems = nullptr;      // shape can give (fixed addresses for captured runs)
   size_t items_cap = 0;
   int nitems = 0;
   size_t ctl_bytes = 0;
   size_t ws_bytes = 0;
   int num_cu = 0;
+  bool pb = false;              // some instance has per-basis totals
 };
 
 namespace {
@@ -363,31 +499,40 @@ void add_range(std::vector<BItem>& out, int inst, Kind kind, uint8_t var, int64_
   if (count_out) *count_out = c;
 }
 
-// Work items of instance j for one stage (0 counts, 1 check + fold, 2 rho low, 3 rho high).
+// Work items of instance j for one stage (0 per-basis totals, 1 counts, 2 check + fold,
+// 3 rho).
 struct StageCounts {
-  uint32_t counts = 0, fold = 0;
+  uint32_t totals = 0, counts = 0, fold = 0;
 };
 
-void emit_stage(const lre_batch& B, int j, int stage, std::vector<BItem>& out, StageCounts& sc) {
+constexpr int kStages = 4;
+constexpr int64_t kTotalsPerItem = 2048;  // bases per per-basis totals item
+
+void emit_stage(const lre_batch& B, const lre_batch_tiles& t, int j, int stage, std::vector<BItem>& out,
+                StageCounts& sc) {
   const InstMeta& m = B.meta[j];
-  const lre_batch_tiles& t = B.tiles;
   const bool want_rho = !(B.flags & LRE_NO_RHO);
   const uint8_t fp32 = (B.flags & LRE_RHO_FP32) ? V_FP32 : 0;
   const uint8_t mad = m.mad24 ? V_MAD24 : 0;
-  const int32_t c_counts = 1 + 3 * j, c_fold = 2 + 3 * j;
+  const uint8_t pb = m.pb ? V_PB : 0;
+  const int32_t c_counts = 1 + 3 * j, c_fold = 2 + 3 * j, c_tot = 3 + 3 * j;
   if (m.n <= kQ) {  // one tile: the whole instance is one item
     if (stage == 0)
-      add_range(out, j, K_SMALL, (uint8_t)(mad | fp32 | (want_rho ? V_RHO : 0)), 1, 1, -1, 0, -1, nullptr);
+      add_range(out, j, K_SMALL, (uint8_t)(mad | fp32 | pb | (want_rho ? V_RHO : 0)), 1, 1, -1, 0, -1, nullptr);
     return;
   }
   switch (stage) {
-    case 0:  // row groups of 3^7 bases, each with all its outcome tiles
-      add_range(out, j, K_COUNTS, mad, ipow3(m.n - kQ), t.counts_tiles, -1, 0, c_counts, &sc.counts);
+    case 0:  // per-basis totals and their reciprocals
+      if (m.pb) add_range(out, j, K_TOTALS, pb, ipow3(m.n), kTotalsPerItem, -1, 0, c_tot, &sc.totals);
       break;
-    case 1:
-      add_range(out, j, K_FOLD, 0, ipow4(kQ), t.fold_cols, c_counts, sc.counts, want_rho ? c_fold : -1, &sc.fold);
+    case 1:  // row groups of 3^7 bases, each with all its outcome tiles
+      add_range(out, j, K_COUNTS, (uint8_t)(mad | pb), ipow3(m.n - kQ), t.counts_tiles, m.pb ? c_tot : -1,
+                sc.totals, c_counts, &sc.counts);
       break;
     case 2:
+      add_range(out, j, K_FOLD, pb, ipow4(kQ), t.fold_cols, c_counts, sc.counts, want_rho ? c_fold : -1, &sc.fold);
+      break;
+    case 3:
       if (want_rho)
         add_range(out, j, K_RHO, fp32, (int64_t)1 << (m.n - kJ), t.rho_blocks, c_fold, sc.fold, -1, nullptr);
       break;
@@ -396,36 +541,38 @@ void emit_stage(const lre_batch& B, int j, int stage, std::vector<BItem>& out, S
   }
 }
 
-lre_status rebuild(lre_batch& B) {
+// The work list of the plan's instances under work-item shape t.
+std::vector<BItem> list_items(const lre_batch& B, const lre_batch_tiles& t) {
   const int count = (int)B.inst.size();
   std::vector<int> order(count);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return B.meta[a].counts > B.meta[b].counts; });
   std::vector<BItem> items;
   std::vector<StageCounts> sc(count);
-  if (B.tiles.interleave) {
+  if (t.interleave) {
     for (int j : order)
-      for (int s = 0; s < 4; ++s) emit_stage(B, j, s, items, sc[j]);
+      for (int s = 0; s < kStages; ++s) emit_stage(B, t, j, s, items, sc[j]);
   } else {
-    for (int s = 0; s < 4; ++s)
-      for (int j : order) emit_stage(B, j, s, items, sc[j]);
+    for (int s = 0; s < kStages; ++s)
+      for (int j : order) emit_stage(B, t, j, s, items, sc[j]);
   }
-  if (items.size() > (size_t)INT32_MAX) return LRE_E_UNSUPPORTED;
+  return items;
+}
+
+// Upload the list of the plan's current shape into the fixed device list.
+lre_status rebuild(lre_batch& B) {
+  const std::vector<BItem> items = list_items(B, B.tiles);
+  if (items.size() > B.items_cap) return LRE_E_UNSUPPORTED;  // the capacity is the largest list
   DeviceGuard g(B.ctx->device);
   if (!g.ok) return LRE_E_HIP;
   // A run still in flight may read the current list: wait before replacing it.
-  if (B.d_items && hipDeviceSynchronize() != hipSuccess) return LRE_E_HIP;
-  if (items.size() > B.items_cap) {
-    if (B.d_items) (void)hipFree(B.d_items);
-    B.d_items = nullptr;
-    B.items_cap = 0;
-    if (hipMalloc(&B.d_items, items.size() * sizeof(BItem)) != hipSuccess) return LRE_E_HIP;
-    B.items_cap = items.size();
-  }
+  if (hipDeviceSynchronize() != hipSuccess) return LRE_E_HIP;
   if (!items.empty() &&
       hipMemcpy(B.d_items, items.data(), items.size() * sizeof(BItem), hipMemcpyHostToDevice) != hipSuccess)
     return LRE_E_HIP;
-  B.nitems = (int)items.size();
+  const int cnt = (int)items.size();
+  if (hipMemcpy(B.d_nitems, &cnt, sizeof cnt, hipMemcpyHostToDevice) != hipSuccess) return LRE_E_HIP;
+  B.nitems = cnt;
   return LRE_OK;
 }
 
@@ -444,7 +591,7 @@ lre_status lre_batch_plan(lre_ctx* ctx, const lre_instance* inst, int count, uin
     const lre_instance& I = inst[j];
     if (I.n < 1 || !I.counts || !I.coef || !aligned(I.counts, 16) || !aligned(I.coef, 8)) return LRE_E_ARG;
     if (I.n > LRE_BATCH_MAX_QUBITS) return LRE_E_UNSUPPORTED;
-    if (I.shots == 0) return LRE_E_UNSUPPORTED;
+    if (I.shots == 0 && I.n_per_basis && !aligned(I.n_per_basis, 4)) return LRE_E_ARG;
     if ((long double)I.shots * (long double)ipow3(I.n) > (long double)INT32_MAX) return LRE_E_ARG;
     if (want_rho && (!I.rho || !aligned(I.rho, 16))) return LRE_E_ARG;
   }
@@ -471,19 +618,29 @@ lre_status lre_batch_plan(lre_ctx* ctx, const lre_instance* inst, int count, uin
     m.q1 = I.n < kQ ? I.n : kQ;
     m.F = I.n > kQ ? I.n - kQ : 0;
     m.blocks1 = ipow3(I.n - m.q1) << (I.n - m.q1);
-    m.mad24 = m.q1 == kQ && 27ull * I.shots < (1ull << 23);
+    m.pb = I.shots == 0;
+    m.mad24 = !m.pb && m.q1 == kQ && 27ull * I.shots < (1ull << 23);
     m.counts = ipow3(I.n) << I.n;
+    B->pb = B->pb || m.pb;
     BInst& d = B->dinst_host[j];
     d.counts = I.counts;
     d.coef = I.coef;
     d.rho = I.rho;
+    d.nb_in = m.pb ? I.n_per_basis : nullptr;
     d.shots = I.shots;
     d.n = I.n;
     d.q1 = m.q1;
     d.off_part = 0;
     if (m.F > 0) {
       d.off_part = (int64_t)off;
-      off += align256((size_t)m.blocks1 * (size_t)ipow4(kQ) * 4);
+      off += align256((size_t)m.blocks1 * (size_t)ipow4(kQ) * (m.pb ? 8 : 4));
+    }
+    d.off_nb = d.off_inv = 0;
+    if (m.pb) {
+      d.off_nb = (int64_t)off;
+      off += align256((size_t)ipow3(I.n) * 4);
+      d.off_inv = (int64_t)off;
+      off += align256((size_t)ipow3(I.n) * 8);
     }
     d.off_tmp = 0;
     if (want_rho && I.n > kJ) {
@@ -501,6 +658,19 @@ lre_status lre_batch_plan(lre_ctx* ctx, const lre_instance* inst, int count, uin
     delete B;
     return LRE_E_HIP;
   }
+  // The smallest shape (one row group, kBT columns, one row pattern per item) gives
+  // the longest list; the list is allocated once at that length.
+  const size_t cap = list_items(*B, lre_batch_tiles{1, 1, kBT, 1, 0}).size();
+  if (cap > (size_t)INT32_MAX) {
+    lre_batch_destroy(B);
+    return LRE_E_UNSUPPORTED;
+  }
+  if (hipMalloc(&B->d_items, std::max<size_t>(cap, 1) * sizeof(BItem)) != hipSuccess ||
+      hipMalloc(&B->d_nitems, 256) != hipSuccess) {
+    lre_batch_destroy(B);
+    return LRE_E_HIP;
+  }
+  B->items_cap = cap;
   B->tiles = lre_batch_tiles{1, 4, kBT * 16, 1, 0};
   const lre_status s = rebuild(*B);
   if (s != LRE_OK) {
@@ -537,13 +707,19 @@ lre_status lre_batch_run(lre_batch* plan, void* workspace, size_t workspace_byte
   uint32_t* ctl = reinterpret_cast<uint32_t*>(ws);
   const int64_t words = 1 + 3 * (int64_t)plan->inst.size();
   hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, st, ctl, words, 0u);
+  if (plan->pb) {  // binary64 accumulators: one workgroup per CU
+    hipLaunchKernelGGL((batch_kernel<1, true>), dim3((unsigned)plan->num_cu), dim3(kBT), 0, st,
+                       (const BItem*)plan->d_items, (const int*)plan->d_nitems, (const BInst*)plan->d_inst, ws, ctl,
+                       plan->ctx->flags);
+    return hipGetLastError() == hipSuccess ? LRE_OK : LRE_E_HIP;
+  }
   const int workers = plan->num_cu * plan->tiles.workers_per_cu;
   if (plan->tiles.workers_per_cu == 1)
-    hipLaunchKernelGGL(batch_kernel<1>, dim3((unsigned)workers), dim3(kBT), 0, st, (const BItem*)plan->d_items,
-                       plan->nitems, (const BInst*)plan->d_inst, ws, ctl, plan->ctx->flags);
+    hipLaunchKernelGGL((batch_kernel<1, false>), dim3((unsigned)workers), dim3(kBT), 0, st, (const BItem*)plan->d_items,
+                       (const int*)plan->d_nitems, (const BInst*)plan->d_inst, ws, ctl, plan->ctx->flags);
   else
-    hipLaunchKernelGGL(batch_kernel<2>, dim3((unsigned)workers), dim3(kBT), 0, st, (const BItem*)plan->d_items,
-                       plan->nitems, (const BInst*)plan->d_inst, ws, ctl, plan->ctx->flags);
+    hipLaunchKernelGGL((batch_kernel<2, false>), dim3((unsigned)workers), dim3(kBT), 0, st, (const BItem*)plan->d_items,
+                       (const int*)plan->d_nitems, (const BInst*)plan->d_inst, ws, ctl, plan->ctx->flags);
   return hipGetLastError() == hipSuccess ? LRE_OK : LRE_E_HIP;
 }
 
@@ -568,6 +744,7 @@ lre_status lre_batch_tune(lre_batch* plan, void* workspace, size_t workspace_byt
       for (int fc : {kBT * 4, kBT * 16})
         for (int rb : {1, 2, 4})
           for (int il : {0, 1}) {
+            if (w == 2 && plan->pb) continue;  // per-basis plans run one workgroup per CU
             const lre_batch_tiles t{w, ct, fc, rb, il};
             if ((s = lre_batch_set_tiles(plan, &t)) != LRE_OK) goto done;
             if ((s = lre_batch_run(plan, workspace, workspace_bytes, stream)) != LRE_OK) goto done;
@@ -600,6 +777,7 @@ void lre_batch_destroy(lre_batch* plan) {
   {
     DeviceGuard g(plan->ctx->device);
     if (plan->d_items) (void)hipFree(plan->d_items);
+    if (plan->d_nitems) (void)hipFree(plan->d_nitems);
     if (plan->d_inst) (void)hipFree(plan->d_inst);
   }
   delete plan;

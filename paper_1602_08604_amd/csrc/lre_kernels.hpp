@@ -426,13 +426,15 @@ __host__ __device__ constexpr uint32_t stream_slot(uint32_t a) {
 // acc / rs_acc: LDS of NACC accumulators and NROWS row totals.  Every thread of the
 // block calls this (it synchronises the block).
 template <int Q, int THREADS, typename Acc, bool PER_BASIS, Out MODE, bool MAD24, bool PREFETCH = PER_BASIS>
-// check_flags (uniform shots, blocks that cover whole rows, i.e. chunks == 2^(n-Q)): check
-// the row totals against `shots` in the block instead of writing rowpart.
+// check_flags (blocks that cover whole rows, i.e. chunks == 2^(n-Q)): check the row
+// totals in the block, against `shots` or the per-basis totals check_nb, instead of
+// writing rowpart.
 __device__ __forceinline__ void counts_block(const uint16_t* __restrict__ counts, int n, int chunks,
                                              const double* __restrict__ inv_nb, void* __restrict__ out,
                                              uint32_t* __restrict__ rowpart, uint64_t shots, int64_t blk,
                                              int tid, Acc* __restrict__ acc, uint32_t* __restrict__ rs_acc,
-                                             uint32_t* __restrict__ check_flags = nullptr) {
+                                             uint32_t* __restrict__ check_flags = nullptr,
+                                             const uint32_t* __restrict__ check_nb = nullptr, int lrow = -1) {
   using G = StreamGeom<Q>;
   constexpr int GROUPS = THREADS / G::LPC;
   constexpr int LB = G::LB;
@@ -443,7 +445,9 @@ __device__ __forceinline__ void counts_block(const uint16_t* __restrict__ counts
   const int64_t b_hi = blk / runs_per_row;
   const int64_t s_hi0 = (blk % runs_per_row) * chunks;
   const int64_t row0 = b_hi * G::NROWS;
-  const int64_t rowlen = (int64_t)1 << n;
+  // lrow: log2 of the row stride in counts (n unless the tile reads a segment of longer
+  // rows, as a streamed slab does)
+  const int64_t rowlen = (int64_t)1 << (lrow < 0 ? n : lrow);
 
   int32_t sg[G::LL > 0 ? G::LL : 1];
   lane_signs<G::LL>(lam, sg);
@@ -709,9 +713,12 @@ __device__ __forceinline__ void counts_block(const uint16_t* __restrict__ counts
   }
 
   if (check_flags) {
-    // The block covered every outcome of its rows: check the totals here (uniform shots).
-    for (int i = tid; i < G::NROWS; i += THREADS)
-      if (rs_acc[i] != (uint32_t)shots) atomicOr(check_flags, (uint32_t)FLAG_SHOTS);
+    // The block covered every outcome of its rows: check the totals here, against the
+    // uniform shots or (check_nb) the per-basis totals.
+    for (int i = tid; i < G::NROWS; i += THREADS) {
+      const uint32_t want = check_nb ? check_nb[row0 + i] : (uint32_t)shots;
+      if (rs_acc[i] != want) atomicOr(check_flags, (uint32_t)FLAG_SHOTS);
+    }
   } else {
     uint32_t* __restrict__ rp = rowpart + blk * G::NROWS;
     for (int i = tid; i < G::NROWS; i += THREADS) rp[i] = rs_acc[i];
@@ -722,11 +729,12 @@ template <int Q, int THREADS, typename Acc, bool PER_BASIS, Out MODE, bool MAD24
           bool PREFETCH = PER_BASIS>
 __global__ __launch_bounds__(THREADS, MINWAVES) void fold_counts_stream_kernel(
     const uint16_t* __restrict__ counts, int n, int chunks, const double* __restrict__ inv_nb,
-    void* __restrict__ out, uint32_t* __restrict__ rowpart, uint64_t shots) {
+    void* __restrict__ out, uint32_t* __restrict__ rowpart, uint64_t shots, int lrow) {
   __shared__ Acc acc[StreamGeom<Q>::NACC];
   __shared__ uint32_t rs_acc[StreamGeom<Q>::NROWS];
   counts_block<Q, THREADS, Acc, PER_BASIS, MODE, MAD24, PREFETCH>(counts, n, chunks, inv_nb, out, rowpart, shots,
-                                                                 blockIdx.x, threadIdx.x, acc, rs_acc);
+                                                                 blockIdx.x, threadIdx.x, acc, rs_acc, nullptr,
+                                                                 nullptr, lrow);
 }
 
 // ---------------------------------------------------------------------------------
@@ -769,7 +777,7 @@ __device__ __forceinline__ uint32_t mfma_slot(uint32_t a) {
 template <int THREADS, typename Acc, bool PER_BASIS, Out MODE>
 __global__ __launch_bounds__(THREADS) void fold_counts_mfma_kernel(
     const uint16_t* __restrict__ counts, int n, int chunks, const uint32_t* __restrict__ nb,
-    void* __restrict__ out, uint32_t* __restrict__ rowpart, uint64_t shots) {
+    void* __restrict__ out, uint32_t* __restrict__ rowpart, uint64_t shots, int lrow) {
   constexpr int Q = 7;
   constexpr int NACC = 1 << (2 * Q);
   constexpr int NROWS = 2187;   // 3^7
@@ -786,7 +794,7 @@ __global__ __launch_bounds__(THREADS) void fold_counts_mfma_kernel(
   const int64_t b_hi = blockIdx.x / runs_per_row;
   const int64_t s_hi0 = (blockIdx.x % runs_per_row) * chunks;
   const int64_t row0 = b_hi * NROWS;
-  const int64_t rowlen = (int64_t)1 << n;
+  const int64_t rowlen = (int64_t)1 << lrow;   // row stride (n, or more for a slab segment)
 
   // A operand: H64 rows 16 mb + col, K slots 16 g + j.
   lre_v4i hA[4];
@@ -1235,6 +1243,65 @@ static __global__ void check_rows_kernel(const uint32_t* __restrict__ rowpart, i
                                   int64_t nbases, uint32_t* __restrict__ flags) {
   const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (b < nbases) check_row(rowpart, rows, runs, nb, shots, b, flags);
+}
+
+// ---------------------------------------------------------------------------------
+// Streamed estimation: the counts arrive in slabs of consecutive bases (fixed letters of
+// the top h qubits).  Each slab is cut into its 2^h outcome segments (fixed outcome bits
+// of the top h qubits); a segment is an instance of n - h qubits whose rows are read with
+// the stride of the full rows, and goes through the same passes as any instance, ending
+// in unnormalised sums V[s_top][a'].  The top qubits are then folded into the
+// coefficient array, which accumulates over the slabs.
+
+// Row totals of a slab: sum the parts every segment's counts pass wrote.
+static __global__ void check_rows_seg_kernel(const uint32_t* __restrict__ rowpart, int64_t seg_stride, int nseg,
+                                             int64_t rows, int64_t runs, const uint32_t* __restrict__ nb,
+                                             uint64_t shots, int64_t nbases, uint32_t* __restrict__ flags) {
+  const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (b >= nbases) return;
+  const int64_t grp = b / rows, j = b % rows;
+  uint64_t tot = 0;
+  for (int sg = 0; sg < nseg; ++sg)
+    for (int64_t r = 0; r < runs; ++r) tot += rowpart[sg * seg_stride + (grp * runs + r) * rows + j];
+  const uint64_t want = shots ? shots : (uint64_t)nb[b];
+  if (tot != want) atomicOr(flags, (uint32_t)FLAG_SHOTS);
+  if (!shots && want == 0) atomicOr(flags, (uint32_t)FLAG_EMPTY);
+}
+
+// Fold of the top H qubits of one slab into the accumulator: for every column a' (the
+// letters of the other qubits) and subset m of the top qubits,
+//   coef[a_top(m) * ncols + a'] += sum_s (-1)^{|s & m|} V[s][a'],
+// a_top(m) carrying letter b_k + 1 at the top qubits in m and I at the others (the
+// one-qubit Gamma vectors of Sec. III; the slab fixes the top letters b_k).  Bit / digit
+// p of s, m and of the packed letters `atop` belongs to the same qubit (p = 0 lowest).
+// Integer sums (uniform shots) stay exact: every value is an integer below 2^53.
+template <int H, typename T>
+__global__ __launch_bounds__(256) void stream_top_fold_kernel(const T* __restrict__ V, double* __restrict__ coef,
+                                                              int64_t ncols, uint32_t atop) {
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (c >= ncols) return;
+  double x[1 << H];
+#pragma unroll
+  for (int sg = 0; sg < (1 << H); ++sg) x[sg] = acc_to_double(V[(int64_t)sg * ncols + c]);
+  wht_regs<H>(x);
+#pragma unroll
+  for (int m = 0; m < (1 << H); ++m) {
+    uint32_t a = 0;
+#pragma unroll
+    for (int p = 0; p < H; ++p)
+      if ((m >> p) & 1) a |= ((atop >> (2 * p)) & 3u) << (2 * p);
+    double* dst = coef + (int64_t)a * ncols + c;
+    *dst += x[m];
+  }
+}
+
+// The accumulated sums T_i divided by (X^T X)_ii = 3^{n - w(i)} (and by the shots in
+// uniform mode), in place: the coefficients e_i.
+static __global__ void stream_finish_kernel(double* __restrict__ coef, int n, uint64_t shots, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= count) return;
+  const int w = pauli_weight((uint64_t)i);
+  coef[i] = shots ? coef[i] / (pow3d(n - w) * (double)shots) : coef[i] / pow3d(n - w);
 }
 
 // ---------------------------------------------------------------------------------

@@ -30,13 +30,15 @@ LRE_E_EIG = 8
 LRE_NO_RHO = 0x1
 LRE_RHO_FP32 = 0x2
 LRE_WHT_MFMA = 0x4
+LRE_STREAM_HOST = 0x8
+LRE_STREAM_MAX_QUBITS = 15
 LRE_MAX_QUBITS = 14
 LRE_BATCH_MAX_QUBITS = 9
 
 
 class lre_instance(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("counts", ctypes.c_void_p), ("shots", ctypes.c_uint64),
-                ("coef", ctypes.c_void_p), ("rho", ctypes.c_void_p)]
+                ("n_per_basis", ctypes.c_void_p), ("coef", ctypes.c_void_p), ("rho", ctypes.c_void_p)]
 
 
 class lre_batch_tiles(ctypes.Structure):
@@ -104,6 +106,24 @@ def lib():
         L.lre_stream_copy.restype = I
         L.lre_batch_destroy.argtypes = [P]
         L.lre_batch_destroy.restype = None
+        L.lre_stream_create.argtypes = [P, I, I, U64, U32, ctypes.POINTER(P)]
+        L.lre_stream_create.restype = I
+        L.lre_stream_workspace_bytes.argtypes = [P]
+        L.lre_stream_workspace_bytes.restype = SZ
+        L.lre_stream_begin.argtypes = [P, P, P, SZ, P]
+        L.lre_stream_begin.restype = I
+        L.lre_stream_push.argtypes = [P, I64, P, P, P, SZ, P]
+        L.lre_stream_push.restype = I
+        L.lre_stream_push_host.argtypes = [P, I64, P, P, P, SZ, P]
+        L.lre_stream_push_host.restype = I
+        L.lre_stream_finish.argtypes = [P, P, P, SZ, P]
+        L.lre_stream_finish.restype = I
+        L.lre_stream_destroy.argtypes = [P]
+        L.lre_stream_destroy.restype = None
+        L.lre_povm_workspace_bytes.argtypes = [I, U32]
+        L.lre_povm_workspace_bytes.restype = SZ
+        L.lre_povm_estimate.argtypes = [P, I, P, P, P, P, P, SZ, U32, P]
+        L.lre_povm_estimate.restype = I
         _lib_handle = L
     return _lib_handle
 
@@ -190,6 +210,41 @@ def estimate(counts: torch.Tensor, shots: int, n_per_basis: torch.Tensor | None 
         ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), int(flags),
         ctypes.c_void_p(_stream(dev)))
     _ok(st, "lre_estimate")
+    if check:
+        check_flags(dev)
+    return coef, rho
+
+
+def povm_estimate(counts: torch.Tensor, G, flags: int = 0, coef: torch.Tensor | None = None,
+                  rho: torch.Tensor | None = None, workspace: torch.Tensor | None = None, check: bool = True):
+    """lre_povm_estimate (reduced measurement set): counts uint16 device [4^n] (or any
+    contiguous shape with 4^n elements), G the 4 x 4 Pauli components Tr(E_j sigma_a) of
+    the per-qubit operators (array-like or float64 device tensor).  Returns (coef, rho)."""
+    if counts.dtype not in (torch.uint16, torch.int16) or not counts.is_cuda or not counts.is_contiguous():
+        raise ValueError("counts must be a contiguous uint16 device tensor")
+    m = counts.numel()
+    n = (m.bit_length() - 1) // 2
+    if m != 4 ** n or not 1 <= n <= LRE_MAX_QUBITS:
+        raise ValueError("counts must hold 4^n outcomes, 1 <= n <= 14")
+    dev = counts.device
+    g = torch.as_tensor(G, dtype=torch.float64).to(dev).contiguous()
+    if g.numel() != 16:
+        raise ValueError("G must be 4 x 4")
+    d = 1 << n
+    if coef is None:
+        coef = torch.empty(4 ** n, dtype=torch.float64, device=dev)
+    want_rho = not (flags & LRE_NO_RHO)
+    if want_rho and rho is None:
+        rho = torch.empty((d, d), dtype=torch.complex64 if flags & LRE_RHO_FP32 else torch.complex128,
+                          device=dev)
+    wsb = int(lib().lre_povm_workspace_bytes(n, int(flags)))
+    if workspace is None:
+        workspace = torch.empty(max(wsb, 1), dtype=torch.uint8, device=dev)
+    _ok(lib().lre_povm_estimate(ctypes.c_void_p(context(dev.index)), n, ctypes.c_void_p(counts.data_ptr()),
+                                ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(coef.data_ptr()),
+                                ctypes.c_void_p(rho.data_ptr() if want_rho else None),
+                                ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), int(flags),
+                                ctypes.c_void_p(_stream(dev))), "lre_povm_estimate")
     if check:
         check_flags(dev)
     return coef, rho
@@ -296,18 +351,23 @@ def set_stage_events(events, device=None):
 
 
 class Batch:
-    """lre_batch_*: many instances (n <= 9, uniform shots each) in one persistent launch.
+    """lre_batch_*: many instances (n <= 9) in one persistent launch.
 
-    counts: list of uint16 device tensors [3^n, 2^n]; shots: list of ints.  Output tensors
-    are allocated unless given (coef float64 [4^n]; rho complex [2^n, 2^n] unless
-    LRE_NO_RHO).  The plan keeps references to every tensor it points to."""
+    counts: list of uint16 device tensors [3^n, 2^n]; shots: list of ints (0 = per-basis
+    totals, then n_per_basis[j] is a 32-bit device tensor [3^n] or None for the row
+    sums).  Output tensors are allocated unless given (coef float64 [4^n]; rho complex
+    [2^n, 2^n] unless LRE_NO_RHO).  The plan keeps references to every tensor it points
+    to."""
 
-    def __init__(self, counts, shots, flags=0, coefs=None, rhos=None):
+    def __init__(self, counts, shots, flags=0, coefs=None, rhos=None, n_per_basis=None):
         if len(counts) != len(shots) or not counts:
             raise ValueError("counts and shots must be non-empty lists of equal length")
         self.flags = int(flags)
         self.counts = list(counts)
         self.shots = [int(x) for x in shots]
+        self.nb = list(n_per_basis) if n_per_basis is not None else [None] * len(self.counts)
+        if len(self.nb) != len(self.counts):
+            raise ValueError("n_per_basis must have one entry per instance")
         dev = self.counts[0].device
         self.device = dev
         want_rho = not (flags & LRE_NO_RHO)
@@ -325,6 +385,11 @@ class Batch:
             arr[j].n = n
             arr[j].counts = self.counts[j].data_ptr()
             arr[j].shots = self.shots[j]
+            nb = self.nb[j]
+            if nb is not None and (nb.dtype not in (torch.int32, torch.uint32) or not nb.is_cuda
+                                   or nb.numel() != 3 ** n or not nb.is_contiguous()):
+                raise ValueError("n_per_basis entries must be contiguous 32-bit device tensors of length 3^n")
+            arr[j].n_per_basis = nb.data_ptr() if nb is not None else None
             arr[j].coef = self.coefs[j].data_ptr()
             arr[j].rho = self.rhos[j].data_ptr() if self.rhos[j] is not None else None
         h = ctypes.c_void_p()
@@ -374,6 +439,96 @@ class Batch:
         if getattr(self, "_h", None):
             lib().lre_batch_destroy(ctypes.c_void_p(self._h))
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Stream:
+    """lre_stream_*: an estimate whose counts arrive slab by slab (slab k: the 3^(n-h)
+    bases whose top h qubits carry the letters of k's base-3 digits, uint16 [3^(n-h), 2^n]).
+
+    begin() clears the coefficient accumulator; push(k, counts) takes a device slab,
+    push_host(k, counts) a host (CPU) tensor, copied by the library into its staging
+    slab (flags must include LRE_STREAM_HOST); finish() returns (coef, rho)."""
+
+    def __init__(self, n: int, h: int, shots: int, flags: int = 0, device=None):
+        self.n, self.h, self.shots, self.flags = int(n), int(h), int(shots), int(flags)
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device) \
+            if not isinstance(device, torch.device) else device
+        self.rows = 3 ** (self.n - self.h)
+        hdl = ctypes.c_void_p()
+        _ok(lib().lre_stream_create(ctypes.c_void_p(context(self.device.index)), self.n, self.h, self.shots,
+                                    self.flags, ctypes.byref(hdl)), "lre_stream_create")
+        self._h = hdl.value
+        self._ws = None
+        self.coef = None
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(lib().lre_stream_workspace_bytes(ctypes.c_void_p(self._h)))
+
+    def workspace(self):
+        if self._ws is None or self._ws.numel() < self.workspace_bytes:
+            self._ws = torch.empty(max(1, self.workspace_bytes), dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def _args(self):
+        ws = self.workspace()
+        return ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(_stream(self.device))
+
+    def begin(self, coef: torch.Tensor | None = None) -> torch.Tensor:
+        if coef is None:
+            coef = torch.empty(4 ** self.n, dtype=torch.float64, device=self.device)
+        if coef.dtype != torch.float64 or coef.numel() != 4 ** self.n or not coef.is_contiguous():
+            raise ValueError("coef must be a contiguous float64 device tensor of length 4^n")
+        self.coef = coef
+        _ok(lib().lre_stream_begin(ctypes.c_void_p(self._h), ctypes.c_void_p(coef.data_ptr()), *self._args()),
+            "lre_stream_begin")
+        return coef
+
+    def _check_slab(self, counts, nb, host):
+        if counts.dtype not in (torch.uint16, torch.int16) or tuple(counts.shape) != (self.rows, 1 << self.n) \
+                or not counts.is_contiguous() or counts.is_cuda == host:
+            raise ValueError(f"slab must be a contiguous uint16 {'host' if host else 'device'} tensor "
+                             f"of shape ({self.rows}, {1 << self.n})")
+        if nb is not None and (nb.dtype not in (torch.int32, torch.uint32) or nb.numel() != self.rows
+                               or not nb.is_contiguous() or nb.is_cuda == host):
+            raise ValueError("n_per_basis must be a contiguous 32-bit tensor of length 3^(n-h) beside the slab")
+
+    def push(self, slab: int, counts: torch.Tensor, n_per_basis: torch.Tensor | None = None):
+        self._check_slab(counts, n_per_basis, host=False)
+        _ok(lib().lre_stream_push(ctypes.c_void_p(self._h), int(slab), ctypes.c_void_p(counts.data_ptr()),
+                                  ctypes.c_void_p(n_per_basis.data_ptr() if n_per_basis is not None else None),
+                                  *self._args()), "lre_stream_push")
+
+    def push_host(self, slab: int, counts: torch.Tensor, n_per_basis: torch.Tensor | None = None):
+        self._check_slab(counts, n_per_basis, host=True)
+        _ok(lib().lre_stream_push_host(ctypes.c_void_p(self._h), int(slab), ctypes.c_void_p(counts.data_ptr()),
+                                       ctypes.c_void_p(n_per_basis.data_ptr() if n_per_basis is not None else None),
+                                       *self._args()), "lre_stream_push_host")
+
+    def finish(self, rho: torch.Tensor | None = None, check: bool = True):
+        want_rho = not (self.flags & LRE_NO_RHO)
+        d = 1 << self.n
+        if want_rho and rho is None:
+            rho = torch.empty((d, d), dtype=torch.complex64 if self.flags & LRE_RHO_FP32 else torch.complex128,
+                              device=self.device)
+        _ok(lib().lre_stream_finish(ctypes.c_void_p(self._h), ctypes.c_void_p(rho.data_ptr() if want_rho else None),
+                                    *self._args()), "lre_stream_finish")
+        if check:
+            check_flags(self.device)
+        coef, self.coef = self.coef, None
+        return coef, rho
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().lre_stream_destroy(ctypes.c_void_p(self._h))
+            self._h = None
+        self._ws = None
 
     def __del__(self):
         try:

@@ -144,9 +144,6 @@ def test_batch_tune_keeps_results():
 def test_batch_errors():
     print("[batch errors]", flush=True)
     counts, shots = _instances(16, [4, 7])
-    with pytest.raises(L.LreError) as e:
-        L.Batch(counts, [shots[0], 0])
-    assert e.value.status == L.LRE_E_UNSUPPORTED
     big = torch.zeros((3 ** 10, 2 ** 10), dtype=torch.uint16, device=DEV)
     with pytest.raises(L.LreError) as e:
         L.Batch([big], [1])
@@ -166,4 +163,115 @@ def test_batch_errors():
     assert e.value.status == L.LRE_E_SHOTS
     coef, _ = _single(counts[0], shots[0])
     assert torch.equal(b.coefs[0], coef)
+    b.close()
+
+
+def test_batch_graph_survives_retune():
+    """A launch captured before lre_batch_set_tiles replays the new work list (the list
+    keeps its address and the kernel reads the item count from device memory)."""
+    print("[batch graph + retune]", flush=True)
+    counts, shots = _instances(17, [9, 8, 9, 7, 4, 8])
+    b = L.Batch(counts, shots)
+    b.set_tiles(1, 4, 432 * 16, 1, 0)
+    b.run(check=True)
+    want_c = [c.clone() for c in b.coefs]
+    want_r = [r.clone() for r in b.rhos]
+    b.workspace()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        b.run()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        b.run()
+    items0 = b.tiles["items"]
+    for shape in ((1, 1, 432, 4, 1), (1, 2, 432 * 4, 2, 0), (1, 4, 432 * 16, 1, 0)):
+        b.set_tiles(*shape)
+        print(f"  retuned to {b.tiles} (captured with {items0} items)", flush=True)
+        for c in b.coefs:
+            c.zero_()
+        for r in b.rhos:
+            r.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        L.check_flags(DEV)
+        for j in range(len(counts)):
+            assert torch.equal(b.coefs[j], want_c[j]), f"{shape}: coef {j}"
+            assert torch.equal(b.rhos[j], want_r[j]), f"{shape}: rho {j}"
+    b.close()
+
+
+def test_batch_per_basis():
+    """Per-basis totals inside a batch (shots = 0): N_b given or taken from the rows,
+    against the single-instance per-basis estimate (1e-12) and the oracle (1e-12),
+    mixed with uniform-shot instances (those stay bit-identical)."""
+    print("[batch per-basis]", flush=True)
+    import tomo_inputs.gpu as tg
+    ns = [9, 3, 8, 7, 5, 9, 1, 8]
+    rng = np.random.default_rng(18)
+    counts, nbs, shots = [], [], []
+    for j, n in enumerate(ns):
+        s = int(rng.integers(100, 3000))
+        c = tg.haar_multinomial_counts(n, s, 18000 + j, device=DEV).to(torch.int32)
+        if j % 2 == 0:              # uneven totals: add 0..5 counts to each basis's first outcome
+            c[:, 0] += torch.from_numpy(rng.integers(0, 6, size=3 ** n).astype(np.int32)).to(DEV)
+        c = c.to(torch.uint16)
+        counts.append(c)
+        nb = c.to(torch.int64).sum(dim=1).to(torch.int32)
+        if j % 2 == 0:
+            shots.append(0)
+            nbs.append(nb if j % 4 == 0 else None)
+        else:
+            shots.append(s)
+            nbs.append(None)
+    for flags in (0, L.LRE_RHO_FP32):
+        b = L.Batch(counts, shots, flags=flags, n_per_basis=nbs)
+        b.run(check=True)
+        for j, n in enumerate(ns):
+            coef, rho = L.estimate(counts[j], shots[j], n_per_basis=nbs[j], flags=flags)
+            if shots[j]:
+                assert torch.equal(b.coefs[j], coef), f"instance {j}"
+                assert torch.equal(b.rhos[j], rho), f"instance {j}"
+                continue
+            assert (b.coefs[j] - coef).abs().max().item() <= TOL, f"instance {j}"
+            tol_r = TOL if flags == 0 else 1e-6
+            assert (b.rhos[j].to(torch.complex128) - rho.to(torch.complex128)).abs().max().item() <= tol_r
+            host = counts[j].cpu().numpy()
+            e = b.coefs[j].cpu().numpy()
+            idx = np.arange(4 ** n) if n <= 6 else np.concatenate(
+                [[0, 4 ** n - 1], np.random.default_rng(j).integers(0, 4 ** n, 300)])
+            ref = oracle.coefs(n, host, 0, idx=idx)
+            assert np.max(np.abs(e[idx] - ref)) <= TOL, f"instance {j}"
+        b.tune(reps=1)
+        b.run(check=True)
+        for j in range(len(ns)):
+            coef, _ = L.estimate(counts[j], shots[j], n_per_basis=nbs[j], flags=flags)
+            assert (b.coefs[j] - coef).abs().max().item() <= TOL
+        b.close()
+
+
+def test_batch_per_basis_errors():
+    """Per-basis data errors in a batch: declared totals that differ from the row sums
+    (LRE_E_SHOTS) and an empty basis (LRE_E_EMPTY_BASIS)."""
+    print("[batch per-basis errors]", flush=True)
+    counts, shots = _instances(19, [8, 5])
+    nb = counts[0].to(torch.int64).sum(dim=1).to(torch.int32)
+    nb[7] += 1
+    b = L.Batch(counts, [0, 0], n_per_basis=[nb, None])
+    b.run()
+    with pytest.raises(L.LreError) as e:
+        L.check_flags(DEV)
+    assert e.value.status == L.LRE_E_SHOTS
+    b.close()
+    empty = counts[1].to(torch.int32)
+    empty[4] = 0
+    empty = empty.to(torch.uint16)
+    b = L.Batch([counts[0], empty], [0, 0])
+    b.run()
+    with pytest.raises(L.LreError) as e:
+        L.check_flags(DEV)
+    assert e.value.status == L.LRE_E_EMPTY_BASIS
     b.close()
