@@ -105,6 +105,26 @@ lre_status lre_estimate(lre_ctx* ctx, int n, const uint16_t* counts, uint64_t sh
                         const uint32_t* n_per_basis, double* coef, void* rho, void* workspace,
                         size_t workspace_bytes, uint32_t flags, void* stream);
 
+/* lre_estimate without a workspace argument, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Arguments, results and errors are those of lre_estimate; the workspace
+ * is a static device array of LRE_NOALLOC_SCRATCH_BYTES bytes that the library holds
+ * on every device it runs on until the process ends (its per-device address is
+ * resolved by lre_create).  The call allocates nothing and frees nothing.
+ *   - Requests whose lre_workspace_bytes(n, shots, flags) exceed
+ *     LRE_NOALLOC_SCRATCH_BYTES return LRE_E_WORKSPACE before any launch (with
+ *     64 MiB: every n <= 10, any shots and flags).
+ *   - Within a process, every call on one device shares that device's array, whatever
+ *     the context: calls that overlap in time on one device (different streams,
+ *     threads or contexts of that device) race and their results are unspecified.
+ *     Order them on one stream.  The array needs no clearing between calls (no
+ *     kernel of the path reads workspace it has not written in the same call).
+ *   - LRE_E_HIP if lre_create could not resolve the array's address. */
+#define LRE_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+lre_status lre_estimate_noalloc(lre_ctx* ctx, int n, const uint16_t* counts, uint64_t shots,
+                                const uint32_t* n_per_basis, double* coef, void* rho, uint32_t flags,
+                                void* stream);
+
 /* Synchronise `stream`, read and clear the context's device flag word.  Returns
  * LRE_E_SHOTS, LRE_E_EMPTY_BASIS, LRE_E_TIMEOUT, LRE_E_HIP or LRE_OK. */
 lre_status lre_check(lre_ctx* ctx, void* stream);

@@ -20,6 +20,12 @@ using lre_detail::DeviceGuard;
 using lre_detail::record_stage;
 
 
+// Workspace of lre_estimate_noalloc: one copy per device, held until the process
+// ends.  Host code never passes this name to a kernel (on the host it is a stand-in,
+// not a device address); it uses the per-device address lre_create resolves with
+// hipGetSymbolAddress, kept in lre_ctx::scratch.
+static __device__ __align__(256) char scratch[LRE_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 constexpr int kMaxQ1 = 7;     // qubits folded by the counts pass
@@ -537,6 +543,11 @@ lre_status lre_create(lre_ctx** out, int hip_device) {
   for (auto& e : c->stage_events) e = nullptr;
   if (hipMalloc(&c->flags, 64) != hipSuccess) { delete c; return LRE_E_HIP; }
   if (hipMemset(c->flags, 0, 64) != hipSuccess) { (void)hipFree(c->flags); delete c; return LRE_E_HIP; }
+  // This device's copy of the static scratch array (device `hip_device` is current).
+  void* sp = nullptr;
+  const hipError_t se = hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch));
+  c->scratch_status = (int)se;
+  c->scratch = se == hipSuccess ? static_cast<char*>(sp) : nullptr;
   *out = c;
   return LRE_OK;
 }
@@ -560,6 +571,16 @@ lre_status lre_estimate(lre_ctx* ctx, int n, const uint16_t* counts, uint64_t sh
                         size_t workspace_bytes, uint32_t flags, void* stream) {
   return estimate_impl(ctx, n, counts, shots, n_per_basis, coef, rho, workspace, workspace_bytes, flags,
                        stream);
+}
+
+lre_status lre_estimate_noalloc(lre_ctx* ctx, int n, const uint16_t* counts, uint64_t shots,
+                                const uint32_t* n_per_basis, double* coef, void* rho, uint32_t flags,
+                                void* stream) {
+  if (!ctx || n < 1 || n > LRE_MAX_QUBITS) return LRE_E_ARG;
+  if (lre_workspace_bytes(n, shots, flags) > (size_t)LRE_NOALLOC_SCRATCH_BYTES) return LRE_E_WORKSPACE;
+  if (!ctx->scratch) return LRE_E_HIP;
+  return estimate_impl(ctx, n, counts, shots, n_per_basis, coef, rho, ctx->scratch,
+                       (size_t)LRE_NOALLOC_SCRATCH_BYTES, flags, stream);
 }
 
 lre_status lre_set_stage_events(lre_ctx* ctx, void* const* events, int count) {

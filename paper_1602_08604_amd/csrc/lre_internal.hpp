@@ -10,6 +10,9 @@ struct lre_ctx {
   hipEvent_t stage_events[4];   // optional profiling events (lre_set_stage_events)
   int n_stage_events;
   void* blas = nullptr;         // rocBLAS handle of lre_project, created on first use
+  char* scratch = nullptr;      // this device's address of the static scratch array
+                                // (lre_estimate_noalloc), resolved by lre_create
+  int scratch_status = 0;       // hipError_t of that lookup
 };
 
 namespace lre_detail {

@@ -33,6 +33,7 @@ LRE_WHT_MFMA = 0x4
 LRE_STREAM_HOST = 0x8
 LRE_STREAM_MAX_QUBITS = 15
 LRE_MAX_QUBITS = 14
+LRE_NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
 LRE_BATCH_MAX_QUBITS = 9
 
 
@@ -76,6 +77,8 @@ def lib():
         L.lre_workspace_bytes.restype = SZ
         L.lre_estimate.argtypes = [P, I, P, U64, P, P, P, P, SZ, U32, P]
         L.lre_estimate.restype = I
+        L.lre_estimate_noalloc.argtypes = [P, I, P, U64, P, P, P, U32, P]
+        L.lre_estimate_noalloc.restype = I
         L.lre_check.argtypes = [P, P]
         L.lre_check.restype = I
         L.lre_pauli_sums.argtypes = [P, I, P, U64, P, P, SZ, U32, P]
@@ -210,6 +213,31 @@ def estimate(counts: torch.Tensor, shots: int, n_per_basis: torch.Tensor | None 
         ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), int(flags),
         ctypes.c_void_p(_stream(dev)))
     _ok(st, "lre_estimate")
+    if check:
+        check_flags(dev)
+    return coef, rho
+
+
+def estimate_noalloc(counts: torch.Tensor, shots: int, coef: torch.Tensor, rho: torch.Tensor | None,
+                     n_per_basis: torch.Tensor | None = None, flags: int = 0, check: bool = True):
+    """lre_estimate_noalloc: lre_estimate into caller-given outputs with the library's
+    static device scratch as workspace (no device allocation by the call)."""
+    n = _check_counts(counts)
+    dev = counts.device
+    want_rho = not (flags & LRE_NO_RHO)
+    if coef.dtype != torch.float64 or coef.numel() != 4 ** n or not coef.is_contiguous():
+        raise ValueError("coef must be a contiguous float64 tensor of length 4^n")
+    if want_rho and (rho is None or rho.numel() != 4 ** n or not rho.is_contiguous()):
+        raise ValueError("rho must be a contiguous 2^n x 2^n complex tensor")
+    if n_per_basis is not None and (n_per_basis.dtype not in (torch.int32, torch.uint32)
+                                    or n_per_basis.numel() != 3 ** n or not n_per_basis.is_contiguous()):
+        raise ValueError("n_per_basis must be a contiguous 32-bit device tensor of length 3^n")
+    st = lib().lre_estimate_noalloc(
+        ctypes.c_void_p(context(dev.index)), n, ctypes.c_void_p(counts.data_ptr()), int(shots),
+        ctypes.c_void_p(n_per_basis.data_ptr() if n_per_basis is not None else None),
+        ctypes.c_void_p(coef.data_ptr()), ctypes.c_void_p(rho.data_ptr() if want_rho else None),
+        int(flags), ctypes.c_void_p(_stream(dev)))
+    _ok(st, "lre_estimate_noalloc")
     if check:
         check_flags(dev)
     return coef, rho
