@@ -213,6 +213,49 @@ def host_cpu():
     return {"model": model, "logical_cpus": os.cpu_count()}
 
 
+def _omp_set_threads(k):
+    """Thread count of the oracle's OpenMP loops (libgomp, shared by the process)."""
+    try:
+        ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(k))
+    except OSError:
+        pass
+
+
+def _n14_pairs_rate(n, rng, budget_s, threads):
+    """Oracle rate on the 14-qubit workload: coefficients with <= 4 identity letters (at
+    most 81 compatible bases each) in chunks of 48; their rows are regenerated by the C
+    Philox twin (input generation, not timed) and eq. (3) accumulated over the pairs by
+    oracle.accumulate_pairs (OpenMP over pairs) with `threads` threads.  Returns
+    (visited terms per second, coefficients, seconds)."""
+    import numpy as np
+
+    import oracle
+    import tomo_inputs as ti
+    _omp_set_threads(threads)
+    t_acc, visits, ncoef = 0.0, 0, 0
+    while t_acc < budget_s:
+        coefs, bases_all = [], []
+        for _ in range(48):
+            letters = rng.integers(1, 4, size=n)
+            letters[rng.choice(n, size=int(rng.integers(0, 5)), replace=False)] = 0
+            i = int(sum(int(a) * 4 ** (n - 1 - k) for k, a in enumerate(letters)))
+            coefs.append(i)
+            bases_all.append(oracle.compatible_bases(n, i))
+        ub = np.unique(np.concatenate(bases_all))
+        rows, nb = ti.philox_counts_rows_fast(n, SEED14, ub)             # input generation
+        prow = np.concatenate([np.searchsorted(ub, b) for b in bases_all])
+        pcoef = np.concatenate([np.full(len(b), i, dtype=np.int64) for i, b in zip(coefs, bases_all)])
+        pslot = np.concatenate([np.full(len(b), t, dtype=np.int64) for t, b in enumerate(bases_all)])
+        acc = np.zeros(len(coefs), dtype=np.longdouble)
+        t0 = time.perf_counter()
+        oracle.accumulate_pairs(n, rows, ub, nb, prow, pcoef, pslot, acc)
+        oracle.coef_from_acc(n, np.array(coefs, dtype=np.int64), acc)
+        t_acc += time.perf_counter() - t0
+        visits += len(prow) * 2 ** n
+        ncoef += len(coefs)
+    return visits / t_acc, ncoef, t_acc
+
+
 def cpu_baseline(workload, n, shots, counts_dev, coef_dev, budget_s=12.0):
     """Time the CPU oracle (as it stands) on a bounded sample of the same workload and
     extrapolate to the whole step: step (i) visits 12^n (projector, coefficient) terms,
@@ -220,58 +263,48 @@ def cpu_baseline(workload, n, shots, counts_dev, coef_dev, budget_s=12.0):
     import numpy as np
 
     import oracle
-    import tomo_inputs as ti
     rng = np.random.default_rng(7)
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count()))
+    if workload == "n14":
+        # all of the host's threads, then one thread (the step-(ii) terms cost the same
+        # per visit as the step-(i) ones: one multiply-add over a row or an entry's terms)
+        rate_all, nc_all, t_all = _n14_pairs_rate(n, rng, budget_s * 0.5, cores)
+        rate_one, nc_one, t_one = _n14_pairs_rate(n, rng, budget_s * 0.5, 1)
+        _omp_set_threads(cores)
+        terms = 12.0 ** n + 8.0 ** n
+        full_all, full_one = terms / rate_all, terms / rate_one
+        sample = (f"{nc_all} coefficients (<= 81 bases each, rows regenerated by the C Philox twin) "
+                  f"in {t_all:.1f} s on {cores} threads; extrapolated to the whole step "
+                  f"({full_all / 3600:.3g} h for 12^n + 8^n terms)")
+        return {"value": 6.0 ** n / full_all, "unit": "counts/s", "cores": cores, "kind": "oracle",
+                "host": host_cpu(), "sample": sample,
+                "one_core": {"value": 6.0 ** n / full_one, "unit": "counts/s", "cores": 1,
+                             "sample": f"{nc_one} coefficients in {t_one:.1f} s on 1 thread "
+                                       f"({full_one / 3600:.3g} h extrapolated)"}}
     visits_i = 0
     t_i = 0.0
-    coef = None
     ncoef = 0
-    if workload == "n14":
-        t_end = time.time() + budget_s * 0.75
-        while time.time() < t_end:
-            # coefficients with few identity letters (<= 4): at most 81 compatible bases each
-            letters = rng.integers(1, 4, size=n)
-            letters[rng.choice(n, size=int(rng.integers(0, 5)), replace=False)] = 0
-            i = int(sum(int(a) * 4 ** (n - 1 - k) for k, a in enumerate(letters)))
-            bases = oracle.compatible_bases(n, i)
-            rows, nb = ti.philox_counts_rows_fast(n, SEED14, bases)      # input generation
-            t0 = time.perf_counter()
-            oracle.coef_from_rows(n, i, rows, nb)
-            t_i += time.perf_counter() - t0
-            visits_i += len(bases) * 2 ** n
-            ncoef += 1
-        sample = f"{ncoef} coefficients (<= 81 bases each) regenerated by the C Philox twin"
-        threads = 1
-    else:
-        c = counts_dev.cpu().numpy()
-        # batches of 4096 random coefficients until about 3/4 of the budget is spent
-        while t_i < budget_s * 0.75:
-            idx = rng.integers(0, 4 ** n, size=4096)
-            w = np.array([sum(1 for k in range(n) if (int(j) >> (2 * k)) & 3) for j in idx])
-            t0 = time.perf_counter()
-            oracle.coefs(n, c, shots, idx=idx)
-            t_i += time.perf_counter() - t0
-            visits_i += int(np.sum(3.0 ** (n - w))) * 2 ** n
-            ncoef += len(idx)
-        sample = f"{ncoef} random coefficients of the full count tensor"
-        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count()))
-    # step (ii): sampled entries of eq. (4) on the GPU coefficients
-    coef = coef_dev.cpu().numpy() if workload != "n14" else None
-    t_ii, visits_ii = 0.0, 0
-    if coef is not None:
-        r = rng.integers(0, 2 ** n, 2000)
-        cc = rng.integers(0, 2 ** n, 2000)
+    c = counts_dev.cpu().numpy()
+    # batches of 4096 random coefficients until about 3/4 of the budget is spent
+    while t_i < budget_s * 0.75:
+        idx = rng.integers(0, 4 ** n, size=4096)
+        w = np.array([sum(1 for k in range(n) if (int(j) >> (2 * k)) & 3) for j in idx])
         t0 = time.perf_counter()
-        oracle.rho(n, coef, r, cc)
-        t_ii = time.perf_counter() - t0
-        visits_ii = 2000 * 2 ** n
-    rate_i = visits_i / t_i
-    t_full = 12.0 ** n / rate_i
-    if visits_ii:
-        t_full += 8.0 ** n / (visits_ii / t_ii)
-    else:
-        t_full += 8.0 ** n / rate_i  # same inner-loop cost per visited term
-    return {"value": 6.0 ** n / t_full, "unit": "counts/s", "cores": threads, "kind": "oracle", "host": host_cpu(),
+        oracle.coefs(n, c, shots, idx=idx)
+        t_i += time.perf_counter() - t0
+        visits_i += int(np.sum(3.0 ** (n - w))) * 2 ** n
+        ncoef += len(idx)
+    sample = f"{ncoef} random coefficients of the full count tensor"
+    # step (ii): sampled entries of eq. (4) on the GPU coefficients
+    coef = coef_dev.cpu().numpy()
+    r = rng.integers(0, 2 ** n, 2000)
+    cc = rng.integers(0, 2 ** n, 2000)
+    t0 = time.perf_counter()
+    oracle.rho(n, coef, r, cc)
+    t_ii = time.perf_counter() - t0
+    visits_ii = 2000 * 2 ** n
+    t_full = 12.0 ** n / (visits_i / t_i) + 8.0 ** n / (visits_ii / t_ii)
+    return {"value": 6.0 ** n / t_full, "unit": "counts/s", "cores": cores, "kind": "oracle", "host": host_cpu(),
             "sample": f"{sample}; oracle time {t_i + t_ii:.1f} s, extrapolated to the whole "
                       f"step ({t_full / 3600:.3g} h for 12^n + 8^n terms)"}
 
@@ -397,6 +430,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="n14", choices=["n14", "n12", "n8", "batch", "project"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-n12", action="store_true",
+                    help="n14 workload: skip the n = 12 sub-record")
     ap.add_argument("--project-n", type=int, default=12, choices=range(1, 15), metavar="N",
                     help="qubits of the step-(iii) workload (--workload project)")
     ap.add_argument("--no-compare", action="store_true",
@@ -421,15 +456,30 @@ def main():
         return bench_project(args, torch, lre)
     if args.workload == "batch":
         return bench_batch(args, torch, lre)
+    out = bench_estimate(args.workload, args, torch, lre, extras=True)
+    if args.workload == "n14" and not args.no_n12:
+        # the metric names n = 12 too: its step time beside the headline, from the same run
+        torch.cuda.empty_cache()
+        sub = bench_estimate("n12", args, torch, lre, extras=False)
+        out["n12"] = {k: sub[k] for k in ("value", "unit", "ms_per_step", "step_ms", "whole_step_hbm_frac",
+                                          "mfma_vs_plain", "config")}
+        out["n12"]["counts_pass_roofline_frac"] = sub["roofline"]["frac"]
+        out["n12"]["counts_pass_traffic"] = sub["roofline"]["traffic"]
+    print(json.dumps(out), flush=True)
+
+
+def bench_estimate(workload, args, torch, lre, extras):
+    """One workload through lre_estimate: K timed steps of the headline counts-pass form
+    and of the other form (MFMA vs plain), outputs of the two compared."""
     t_gen = time.time()
-    n, counts, shots, nb, desc = make_workload(args.workload, torch)
+    n, counts, shots, nb, desc = make_workload(workload, torch)
     torch.cuda.synchronize()
     t_gen = time.time() - t_gen
     d = 1 << n
     coef = torch.empty(4 ** n, dtype=torch.float64, device="cuda:0")
     rho = torch.empty((d, d), dtype=torch.complex128, device="cuda:0")
     ws = torch.empty(lre.workspace_bytes(n, shots, 0), dtype=torch.uint8, device="cuda:0")
-    print(f"[bench] workload {args.workload}: generated in {t_gen:.1f} s; workspace "
+    print(f"[bench] workload {workload}: generated in {t_gen:.1f} s; workspace "
           f"{ws.numel() / 1e9:.2f} GB", file=sys.stderr, flush=True)
 
     def timed(flags):
@@ -456,7 +506,7 @@ def main():
                "step_ii": [ev.ms(k, 2, 3) for k in range(args.steps)]}
         ev.close()
         mean = lambda v: sum(v) / len(v)
-        print(f"[bench] flags={flags}: {args.steps} steps: {res['ms_step']:.3f} ms/step wall; counts pass "
+        print(f"[bench] {workload} flags={flags}: {args.steps} steps: {res['ms_step']:.3f} ms/step wall; counts pass "
               f"{mean(res['pass1']):.3f} ms, step (i) {mean(res['step_i']):.3f} ms, "
               f"step (ii) {mean(res['step_ii']):.3f} ms", file=sys.stderr, flush=True)
         return res
@@ -464,8 +514,9 @@ def main():
     mfma_ok = n >= 7
     head_flags = lre.LRE_WHT_MFMA if (args.wht == "mfma" and mfma_ok) else 0
     head = timed(head_flags)
+    head_coef = coef.clone() if (mfma_ok and not args.no_compare) else None
     other = timed(0 if head_flags else lre.LRE_WHT_MFMA) if (mfma_ok and not args.no_compare) else None
-    if args.copy_calibration:
+    if args.copy_calibration and extras:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
         dst = torch.empty_like(src)
         torch.neg(src, out=dst)
@@ -477,7 +528,7 @@ def main():
     n_counts = 3 ** n * d
     t_pass1 = sum(pass1) / len(pass1) / 1e3
     achieved = 2.0 * n_counts / t_pass1 / 1e9
-    traffic = measured_traffic(args.workload)
+    traffic = measured_traffic(workload)
     algo_bytes = 2.0 * n_counts + 8.0 * 4 ** n + 16.0 * 4 ** n
     out = {
         "metric": METRIC,
@@ -510,18 +561,25 @@ def main():
         mean = lambda v: sum(v) / len(v)
         # int8 work of the MFMA form: H_64 on two byte limbs = 64 multiply-adds per limb per count
         mfma_tops = 2.0 * 64 * 2 * n_counts / (mean(mfma["pass1"]) / 1e3) / 1e12
+        # the two forms' coefficients, compared here (exact integers with uniform shots;
+        # binary64 sums in LDS-atomic order with per-basis totals)
+        diff = (coef - head_coef).abs().max().item()
+        same = bool(torch.equal(coef, head_coef))
+        del head_coef
         out["mfma_vs_plain"] = {
             "mfma_int8_tops": mfma_tops, "mfma_int8_peak_tops": 5000.0, "mfma_frac": mfma_tops / 5000.0,
             "counts_pass_speedup": mean(plain["pass1"]) / mean(mfma["pass1"]),
             "step_speedup": plain["ms_step"] / mfma["ms_step"],
             "plain_counts_pass_ms": mean(plain["pass1"]), "mfma_counts_pass_ms": mean(mfma["pass1"]),
             "plain_ms_per_step": plain["ms_step"], "mfma_ms_per_step": mfma["ms_step"],
-            "signed_sums": "bit-identical (tests/test_gpu_parity.py)"}
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.workload, n, shots, counts, coef)
-    if not args.no_compare:
+            "coef_bit_identical": same, "coef_max_abs_diff": diff}
+    if extras and not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(workload, n, shots, counts, coef)
+    if extras and not args.no_compare:
+        del counts, ws, rho, coef, nb
+        torch.cuda.empty_cache()
         out["hbm_measured"] = measured_hbm(torch, lre)
-    print(json.dumps(out), flush=True)
+    return out
 
 
 if __name__ == "__main__":

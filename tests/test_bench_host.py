@@ -32,3 +32,12 @@ def test_cpu_baseline_leg_reports_the_oracle():
     assert out["kind"] == "oracle" and out["unit"] == "counts/s"
     assert out["value"] > 0 and out["cores"] >= 1
     assert "random coefficients" in out["sample"]
+
+
+def test_cpu_baseline_n14_all_cores_and_one():
+    """The 14-qubit leg times the oracle on all host threads and on one."""
+    out = bench.cpu_baseline("n14", 14, 0, None, None, budget_s=0.5)
+    assert out["kind"] == "oracle" and out["value"] > 0 and out["cores"] >= 1
+    one = out["one_core"]
+    assert one["cores"] == 1 and one["value"] > 0
+    assert "threads" in out["sample"] and "1 thread" in one["sample"]
