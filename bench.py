@@ -11,7 +11,8 @@ Prints ONE JSON line with throughput (counts/s over the whole step), the rooflin
 the dominant kernel (the counts pass) measured live with HIP events on the stream it
 runs on, and the CPU oracle timed on a bounded sample of the same workload.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload n14|n12|n8|batch|project]
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+                    [--workload n14|n12|n8|batch|project|stream15|povm14]
 """
 from __future__ import annotations
 
@@ -309,6 +310,165 @@ def cpu_baseline(workload, n, shots, counts_dev, coef_dev, budget_s=12.0):
                       f"step ({t_full / 3600:.3g} h for 12^n + 8^n terms)"}
 
 
+SEED15 = 0x16020860415
+
+
+def bench_stream(args, torch, lre):
+    """Streamed estimate at n = 15 (940 GB of counts, beyond device memory): 27 slabs of
+    3^12 bases (34.8 GB each) of the Philox per-basis workload, each generated on the device
+    into one slab buffer (not timed) and pushed (timed with events around every push and
+    the finish).  Then the host path at n = 14 (27 slabs of 5.8 GB): each slab copied from
+    pinned host memory by lre_stream_push_host, against the measured host-to-device rate."""
+    import tomo_inputs.gpu as tg
+    n, h = 15, 3
+    rows = 3 ** (n - h)
+    S = lre.Stream(n, h, 0)
+    S.workspace()
+    slab = torch.empty((rows, 2 ** n), dtype=torch.uint16, device="cuda:0")
+    nb = torch.empty(rows, dtype=torch.int32, device="cuda:0")
+    coef = torch.empty(4 ** n, dtype=torch.float64, device="cuda:0")
+    rho = torch.empty((2 ** n, 2 ** n), dtype=torch.complex128, device="cuda:0")
+    t_push = 0.0
+    S.begin(coef)
+    for k in range(3 ** h):
+        tg.philox_counts(n, SEED15, b_begin=k * rows, b_count=rows, counts=slab, nb=nb)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        S.push(k, slab, nb)
+        e1.record()
+        torch.cuda.synchronize()
+        t_push += e0.elapsed_time(e1)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    S.finish(rho, check=False)
+    e1.record()
+    torch.cuda.synchronize()
+    lre.check_flags("cuda:0")
+    t_fin = e0.elapsed_time(e1)
+    S.close()
+    del slab, nb, coef, rho
+    torch.cuda.empty_cache()
+    ms = t_push + t_fin
+    n_counts = 3 ** n * 2 ** n
+    algo = 2.0 * n_counts + 24.0 * 4 ** n
+    slab_counts = rows * 2 ** n
+    achieved = 2.0 * slab_counts / (t_push / 3 ** h / 1e3) / 1e9   # per push: every pass of the slab
+    print(f"[bench] stream n=15: {3 ** h} slabs pushed in {t_push:.1f} ms, finish {t_fin:.1f} ms", file=sys.stderr,
+          flush=True)
+
+    # host path (n = 14): slabs in pinned host memory
+    n2 = 14
+    rows2 = 3 ** (n2 - h)
+    host = torch.empty((rows2, 2 ** n2), dtype=torch.uint16, pin_memory=True)
+    dev = torch.empty((rows2, 2 ** n2), dtype=torch.uint16, device="cuda:0")
+    nbh = torch.empty(rows2, dtype=torch.int32, pin_memory=True)
+    nbd = torch.empty(rows2, dtype=torch.int32, device="cuda:0")
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    host.copy_(dev)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(3):
+        dev.copy_(host, non_blocking=True)
+    e1.record()
+    torch.cuda.synchronize()
+    h2d = 3 * 2.0 * rows2 * 2 ** n2 / (e0.elapsed_time(e1) / 1e3) / 1e9
+    S2 = lre.Stream(n2, h, 0, flags=lre.LRE_STREAM_HOST)
+    S2.workspace()
+    coef2 = torch.empty(4 ** n2, dtype=torch.float64, device="cuda:0")
+    rho2 = torch.empty((2 ** n2, 2 ** n2), dtype=torch.complex128, device="cuda:0")
+    S2.begin(coef2)
+    t_host = 0.0
+    for k in range(3 ** h):
+        tg.philox_counts(n2, SEED14, b_begin=k * rows2, b_count=rows2, counts=dev, nb=nbd)
+        host.copy_(dev)
+        nbh.copy_(nbd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S2.push_host(k, host, nbh)
+        torch.cuda.synchronize()
+        t_host += time.perf_counter() - t0
+    t0 = time.perf_counter()
+    S2.finish(rho2)
+    t_host += time.perf_counter() - t0
+    S2.close()
+    host_rate = 3 ** n2 * 2 ** n2 / t_host
+    out = {
+        "metric": METRIC + " (streamed, n = 15)", "value": n_counts / (ms / 1e3), "unit": "counts/s",
+        "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32+f64", "data": "synthetic",
+        "config": {"workload": "n=15: 14348907 bases x 32768 outcomes uint16 (940 GB, more than device memory), "
+                               "Philox4x32-10 i.i.d. U{0..12}, per-basis totals; 27 device slabs of 3^12 bases "
+                               "(34.8 GB) generated one at a time (generation not timed) and pushed; coef f64 "
+                               "[4^15] + rho c128 [32768^2]", "n": 15, "h": h, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "one slab push (totals, the 8 segments' counts and later passes, row check, "
+                               "top-qubit fold), timed with events around each push",
+                     "algorithmic_bytes_per_launch": 2.0 * slab_counts},
+        "whole_step_hbm_frac": algo / (ms / 1e3) / (HBM_PEAK_GBS * 1e9),
+        "step_ms": {"pushes": t_push, "finish": t_fin},
+        "host_streamed_n14": {"counts_per_s": host_rate, "s": t_host, "h2d_pinned_gbs": h2d,
+                              "link_bound_counts_per_s": h2d * 1e9 / 2.0,
+                              "how": "27 slabs of 3^11 bases (5.8 GB) copied from pinned host memory by "
+                                     "lre_stream_push_host, wall time of the pushes and the finish"},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_povm(args, torch, lre):
+    """Reduced operator set (Sec. VI) at n = 14: 4^14 outcome counts of the tetrahedral POVM
+    (uniform random counts in [0, 60), seeded), coefficients and rho."""
+    import numpy as np
+    n = 14
+    rng = np.random.default_rng(16044)
+    c = torch.from_numpy(rng.integers(0, 60, size=4 ** n).astype(np.uint16)).to("cuda:0")
+    tet = np.array([[1, 1, 1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]]) / np.sqrt(3.0)
+    G = torch.from_numpy(np.hstack([np.full((4, 1), 0.5), tet / 2])).to("cuda:0")
+    d = 1 << n
+    coef = torch.empty(4 ** n, dtype=torch.float64, device="cuda:0")
+    rho = torch.empty((d, d), dtype=torch.complex128, device="cuda:0")
+    ws = torch.empty(lre.lib().lre_povm_workspace_bytes(n, 0), dtype=torch.uint8, device="cuda:0")
+    for _ in range(args.warmup):
+        lre.povm_estimate(c, G, coef=coef, rho=rho, workspace=ws, check=False)
+    lre.check_flags("cuda:0")
+    ev = StageEvents(args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        lre.set_stage_events(ev.ev[k])
+        lre.povm_estimate(c, G, coef=coef, rho=rho, workspace=ws, check=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lre.set_stage_events(None)
+    lre.check_flags("cuda:0")
+    ms = (t1 - t0) * 1e3 / args.steps
+    t_i = sum(ev.ms(k, 1, 2) for k in range(args.steps)) / args.steps
+    t_ii = sum(ev.ms(k, 2, 3) for k in range(args.steps)) / args.steps
+    ev.close()
+    m = 4 ** n
+    algo_i = 2.0 * m + 8.0 * m
+    out = {
+        "metric": "reduced operator set (Sec. VI): outcomes/s of LRE steps (i) + (ii)", "value": m / (ms / 1e3),
+        "unit": "counts/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "n=14: 4^14 outcome counts uint16 (537 MB) of the tetrahedral POVM on every qubit, "
+                               "uniform random in [0, 60); coef f64 [4^14] + rho c128 [16384^2]", "n": n,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": algo_i / (t_i / 1e3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": algo_i / (t_i / 1e3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "step (i) mode-product passes (povm_low_kernel, povm_high4_kernel x2)",
+                     "algorithmic_bytes_per_launch": algo_i},
+        "step_ms": {"step_i": t_i, "step_ii": t_ii},
+        "whole_step_hbm_frac": (algo_i + 16.0 * m) / (ms / 1e3) / (HBM_PEAK_GBS * 1e9),
+    }
+    print(f"[bench] povm n=14: {ms:.3f} ms/step (step (i) {t_i:.3f} ms, step (ii) {t_ii:.3f} ms)", file=sys.stderr,
+          flush=True)
+    print(json.dumps(out), flush=True)
+
+
 BATCH_SEED = 16042
 
 
@@ -428,7 +588,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="n14", choices=["n14", "n12", "n8", "batch", "project"])
+    ap.add_argument("--workload", default="n14", choices=["n14", "n12", "n8", "batch", "project", "stream15", "povm14"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-n12", action="store_true",
                     help="n14 workload: skip the n = 12 sub-record")
@@ -456,6 +616,10 @@ def main():
         return bench_project(args, torch, lre)
     if args.workload == "batch":
         return bench_batch(args, torch, lre)
+    if args.workload == "stream15":
+        return bench_stream(args, torch, lre)
+    if args.workload == "povm14":
+        return bench_povm(args, torch, lre)
     out = bench_estimate(args.workload, args, torch, lre, extras=True)
     if args.workload == "n14" and not args.no_n12:
         # the metric names n = 12 too: its step time beside the headline, from the same run

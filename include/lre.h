@@ -76,8 +76,9 @@ lre_status lre_create(lre_ctx** out, int hip_device);
 /* Destroy a context created by lre_create (NULL is ignored). */
 void lre_destroy(lre_ctx* ctx);
 
-/* Static, human-readable name of a status code. */
-const char* lre_status_str(int status);
+/* Static, human-readable name of a status code ("unknown status" for a value outside
+ * the enumeration). */
+const char* lre_status_str(lre_status status);
 
 /* Bytes of device workspace lre_estimate needs for this (n, shots, flags); 0 when n
  * is out of range.  shots follows lre_estimate (0 = per-basis totals). */
@@ -149,6 +150,9 @@ lre_status lre_pauli_sums(lre_ctx* ctx, int n, const uint16_t* counts, uint64_t 
 /* Signed outcome sums of selected bases (verification entry):
  * out[j][m] = sum_s c[b_j][s] (-1)^{popcount(s & m)} for m < 2^n, i.e. the per-basis
  * part sum_s c gamma^(b,s)_i of eq. (3) at the coefficient i whose support is m.
+ * flags: 0 (the register / lane butterflies of the plain counts pass) or LRE_WHT_MFMA
+ * (the int8-MFMA 64-outcome transform of the MFMA counts pass, n >= 6; smaller n
+ * returns LRE_E_UNSUPPORTED).
  *   bases : device int64 [num_bases], each in [0, 3^n) (an out-of-range entry yields
  *           an all-zero row and raises LRE_E_ARG through lre_check).
  *   out   : device int32 [num_bases][2^n]. */

@@ -515,7 +515,7 @@ lre_status estimate_impl(lre_ctx* ctx, int n, const uint16_t* counts, uint64_t s
 
 extern "C" {
 
-const char* lre_status_str(int s) {
+const char* lre_status_str(lre_status s) {
   switch (s) {
     case LRE_OK: return "ok";
     case LRE_E_ARG: return "invalid argument";
@@ -526,8 +526,8 @@ const char* lre_status_str(int s) {
     case LRE_E_UNSUPPORTED: return "unsupported request";
     case LRE_E_TIMEOUT: return "a batched run's bounded wait expired";
     case LRE_E_EIG: return "the eigendecomposition of step (iii) did not converge";
-    default: return "unknown status";
   }
+  return "unknown status";
 }
 
 lre_status lre_create(lre_ctx** out, int hip_device) {
@@ -631,7 +631,7 @@ lre_status lre_signed_sums(lre_ctx* ctx, int n, const uint16_t* counts, const in
   if (!ctx || !counts || !bases || !out || n < 1 || n > LRE_MAX_QUBITS || num_bases < 0)
     return LRE_E_ARG;
   if (flags & ~(LRE_WHT_MFMA)) return LRE_E_ARG;
-  if (flags & LRE_WHT_MFMA) return LRE_E_UNSUPPORTED;
+  if ((flags & LRE_WHT_MFMA) && n < 6) return LRE_E_UNSUPPORTED;
   if (!aligned(counts, 16) || !aligned(out, 4) || !aligned(bases, 8)) return LRE_E_ARG;
   if (num_bases == 0) return LRE_OK;
   if (num_bases > INT32_MAX) return LRE_E_ARG;
@@ -639,6 +639,11 @@ lre_status lre_signed_sums(lre_ctx* ctx, int n, const uint16_t* counts, const in
   if (!g.ok) return LRE_E_HIP;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const size_t lds = (size_t)4 << n;
+  if (flags & LRE_WHT_MFMA) {
+    hipLaunchKernelGGL(signed_sums_mfma_kernel, dim3((unsigned)num_bases), dim3(256), lds, st, counts, n, bases, out,
+                       ctx->flags);
+    return hipGetLastError() == hipSuccess ? LRE_OK : LRE_E_HIP;
+  }
   const int q = n < kMaxQ1 ? n : kMaxQ1;
   switch (q) {
 #define LRE_SS(Q)                                                                                  \
@@ -930,13 +935,11 @@ lre_status lre_povm_estimate(lre_ctx* ctx, int n, const uint16_t* counts, const 
 
   record_stage(ctx, 0, st);
   hipLaunchKernelGGL(povm_setup_kernel, dim3(1), dim3(64), 0, st, G, M, total, ctx->flags);
-  const int64_t tb = std::min<int64_t>((count + 255) / 256, 4096);
-  hipLaunchKernelGGL(povm_total_kernel, dim3((unsigned)tb), dim3(256), 0, st, counts, count, total);
-  hipLaunchKernelGGL(povm_check_kernel, dim3(1), dim3(64), 0, st, (const unsigned long long*)total, ctx->flags);
   record_stage(ctx, 1, st);
 
-  // passes: the lowest min(n, 6) digits in one LDS tile, then 4 digits at a time in LDS,
-  // then the remaining 1..3 in registers; the last pass divides by N
+  // passes: the lowest min(n, 6) digits in one LDS tile (which also sums the counts into
+  // N), then 4 digits at a time in LDS, then the remaining 1..3 in registers; the last
+  // pass divides by N
   const int J = n < 6 ? n : 6;
   const int64_t tiles = count >> (2 * J);
   const bool only = J == n;
@@ -945,24 +948,26 @@ lre_status lre_povm_estimate(lre_ctx* ctx, int n, const uint16_t* counts, const 
   case JJ:                                                                                                 \
     if (only)                                                                                              \
       hipLaunchKernelGGL((povm_low_kernel<JJ, true>), dim3((unsigned)tiles), dim3(256), 0, st, counts, coef, \
-                         (const double*)M, (const unsigned long long*)total);                              \
+                         (const double*)M, total, ctx->flags);                                              \
     else                                                                                                   \
       hipLaunchKernelGGL((povm_low_kernel<JJ, false>), dim3((unsigned)tiles), dim3(256), 0, st, counts, coef, \
-                         (const double*)M, (const unsigned long long*)total);                              \
+                         (const double*)M, total, ctx->flags);                                              \
     break;
     LRE_POVM_LOW(1) LRE_POVM_LOW(2) LRE_POVM_LOW(3) LRE_POVM_LOW(4) LRE_POVM_LOW(5) LRE_POVM_LOW(6)
 #undef LRE_POVM_LOW
   }
+  if (!only)
+    hipLaunchKernelGGL(povm_check_kernel, dim3(1), dim3(64), 0, st, (const unsigned long long*)total, ctx->flags);
   int lo = J;
   while (n - lo >= 4) {
     const bool last = n - lo == 4;
     const int64_t blocks = (count >> 8) / kPovmCols;
     if (last)
-      hipLaunchKernelGGL((povm_high4_kernel<true>), dim3((unsigned)blocks), dim3(256), 0, st, coef, n, lo,
-                         (const double*)M, (const unsigned long long*)total);
+      hipLaunchKernelGGL((povm_high4_kernel<true>), dim3((unsigned)blocks), dim3(kPovmHighThreads), 0, st, coef, n,
+                         lo, (const double*)M, (const unsigned long long*)total);
     else
-      hipLaunchKernelGGL((povm_high4_kernel<false>), dim3((unsigned)blocks), dim3(256), 0, st, coef, n, lo,
-                         (const double*)M, (const unsigned long long*)total);
+      hipLaunchKernelGGL((povm_high4_kernel<false>), dim3((unsigned)blocks), dim3(kPovmHighThreads), 0, st, coef, n,
+                         lo, (const double*)M, (const unsigned long long*)total);
     lo += 4;
   }
   if (n > lo) {

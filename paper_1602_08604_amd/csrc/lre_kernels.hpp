@@ -774,6 +774,49 @@ __device__ __forceinline__ uint32_t mfma_slot(uint32_t a) {
   return (d0 << 12) | (d1 << 10) | (d4 << 8) | (d5 << 6) | (d6 << 4) | (d2 << 2) | d3;
 }
 
+// A operand of the 64-point transform for lane (g, col): rows 16 mb + col of H64, K slots
+// 16 g + j, entries +-1 as int8.
+__device__ __forceinline__ void mfma_h64_operand(int col, int g, lre_v4i (&hA)[4]) {
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb) {
+    const int m = 16 * mb + col;
+    int wv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      uint32_t wd = 0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int k = 16 * g + 4 * q + b;
+        const uint32_t v = (__popc((unsigned)(m & k)) & 1) ? 0xFFu : 0x01u;
+        wd |= v << (8 * b);
+      }
+      wv[q] = (int)wd;
+    }
+    hA[mb] = lre_v4i{wv[0], wv[1], wv[2], wv[3]};
+  }
+}
+
+// Walsh-Hadamard transform of 64 outcomes on int8 MFMA, exact in int32: lane (g, col)
+// supplies counts 16 g .. 16 g + 15 of column col's 64-outcome segment in w (uint16
+// pairs) and receives S[mb][r], Walsh index 16 mb + 4 g + r of its column.  Two biased
+// byte limbs per count (c = l0 + 256 l1 + 32896); the bias only reaches Walsh row 0.
+__device__ __forceinline__ void mfma_wht64(const lre_v4i (&hA)[4], const uint32_t (&w)[8], int g,
+                                           int32_t (&S)[4][4]) {
+  const lre_v4i l0 = limb_pack(w, 0x06040200u);
+  const lre_v4i l1 = limb_pack(w, 0x07050301u);
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb) {
+    const lre_v4i z = {0, 0, 0, 0};
+    const lre_v4i d0 = __builtin_amdgcn_mfma_i32_16x16x64_i8(hA[mb], l0, z, 0, 0, 0);
+    const lre_v4i d1 = __builtin_amdgcn_mfma_i32_16x16x64_i8(hA[mb], l1, z, 0, 0, 0);
+    S[mb][0] = d0.x + (d1.x << 8);
+    S[mb][1] = d0.y + (d1.y << 8);
+    S[mb][2] = d0.z + (d1.z << 8);
+    S[mb][3] = d0.w + (d1.w << 8);
+  }
+  if (g == 0) S[0][0] += 32896 * 64;  // bias of the limb encoding (Walsh row 0)
+}
+
 template <int THREADS, typename Acc, bool PER_BASIS, Out MODE>
 __global__ __launch_bounds__(THREADS) void fold_counts_mfma_kernel(
     const uint16_t* __restrict__ counts, int n, int chunks, const uint32_t* __restrict__ nb,
@@ -796,25 +839,8 @@ __global__ __launch_bounds__(THREADS) void fold_counts_mfma_kernel(
   const int64_t row0 = b_hi * NROWS;
   const int64_t rowlen = (int64_t)1 << lrow;   // row stride (n, or more for a slab segment)
 
-  // A operand: H64 rows 16 mb + col, K slots 16 g + j.
   lre_v4i hA[4];
-#pragma unroll
-  for (int mb = 0; mb < 4; ++mb) {
-    const int m = 16 * mb + col;
-    int wv[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      uint32_t wd = 0;
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int k = 16 * g + 4 * q + b;
-        const uint32_t v = (__popc((unsigned)(m & k)) & 1) ? 0xFFu : 0x01u;
-        wd |= v << (8 * b);
-      }
-      wv[q] = (int)wd;
-    }
-    hA[mb] = lre_v4i{wv[0], wv[1], wv[2], wv[3]};
-  }
+  mfma_h64_operand(col, g, hA);
 
   for (int i = tid; i < NACC; i += THREADS) acc[i] = Acc(0);
   for (int i = tid; i < NROWS; i += THREADS) rs_acc[i] = 0;
@@ -860,19 +886,7 @@ __global__ __launch_bounds__(THREADS) void fold_counts_mfma_kernel(
 #pragma unroll
             for (int k = 0; k < 8; ++k) w[k] = 0;
           }
-          const lre_v4i l0 = limb_pack(w, 0x06040200u);
-          const lre_v4i l1 = limb_pack(w, 0x07050301u);
-#pragma unroll
-          for (int mb = 0; mb < 4; ++mb) {
-            const lre_v4i z = {0, 0, 0, 0};
-            const lre_v4i d0 = __builtin_amdgcn_mfma_i32_16x16x64_i8(hA[mb], l0, z, 0, 0, 0);
-            const lre_v4i d1 = __builtin_amdgcn_mfma_i32_16x16x64_i8(hA[mb], l1, z, 0, 0, 0);
-            S[sb][mb][0] = d0.x + (d1.x << 8);
-            S[sb][mb][1] = d0.y + (d1.y << 8);
-            S[sb][mb][2] = d0.z + (d1.z << 8);
-            S[sb][mb][3] = d0.w + (d1.w << 8);
-          }
-          if (g == 0) S[sb][0][0] += 32896 * 64;  // bias of the limb encoding (Walsh row 0)
+          mfma_wht64(hA, w, g, S[sb]);
         }
         // Butterfly on outcome bit 6: S[0] <- m6 = 0, S[1] <- m6 = 1.
 #pragma unroll
@@ -1333,6 +1347,59 @@ __global__ __launch_bounds__(256) void signed_sums_kernel(const uint16_t* __rest
   }
   __syncthreads();
   for (int bit = Q; bit < n; ++bit) {
+    for (int64_t t = tid; t < d / 2; t += 256) {
+      const int64_t lo = ((t >> bit) << (bit + 1)) | (t & (((int64_t)1 << bit) - 1));
+      const int64_t hi = lo | ((int64_t)1 << bit);
+      const int32_t a = srow[lo], c = srow[hi];
+      srow[lo] = a + c;
+      srow[hi] = a - c;
+    }
+    __syncthreads();
+  }
+  for (int64_t t = tid; t < d; t += 256) out[(int64_t)blockIdx.x * d + t] = srow[t];
+}
+
+// The same sums with the int8-MFMA form of the counts pass (n >= 6): the 16 columns of
+// an MFMA are 16 segments of 64 outcomes of the row, transformed by mfma_wht64; the
+// bits above 6 in LDS.  One block (4 waves) per row.
+static __global__ __launch_bounds__(256) void signed_sums_mfma_kernel(const uint16_t* __restrict__ counts, int n,
+                                                               const int64_t* __restrict__ bases,
+                                                               int32_t* __restrict__ out,
+                                                               uint32_t* __restrict__ flags) {
+  extern __shared__ int32_t srow[];
+  const int64_t d = (int64_t)1 << n;
+  const int64_t b = bases[blockIdx.x];
+  const bool ok = b >= 0 && b < ipow3(n);
+  if (!ok && threadIdx.x == 0) atomicOr(flags, (uint32_t)FLAG_ARG);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int col = lane & 15, g = lane >> 4;
+  lre_v4i hA[4];
+  mfma_h64_operand(col, g, hA);
+  const int64_t nseg = d >> 6;
+  for (int64_t seg0 = (int64_t)wave * 16; seg0 < nseg; seg0 += 64) {   // uniform per wave
+    const int64_t seg = seg0 + col;
+    const bool valid = ok && seg < nseg;
+    uint32_t w[8];
+    if (valid) {
+      const uint4* p = reinterpret_cast<const uint4*>(counts + b * d + seg * 64 + 16 * g);
+      const uint4 u0 = p[0], u1 = p[1];
+      w[0] = u0.x; w[1] = u0.y; w[2] = u0.z; w[3] = u0.w;
+      w[4] = u1.x; w[5] = u1.y; w[6] = u1.z; w[7] = u1.w;
+    } else {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) w[k] = 0;
+    }
+    int32_t S[4][4];
+    mfma_wht64(hA, w, g, S);
+    if (seg < nseg) {
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) srow[seg * 64 + 16 * mb + 4 * g + r] = ok ? S[mb][r] : 0;
+    }
+  }
+  __syncthreads();
+  for (int bit = 6; bit < n; ++bit) {
     for (int64_t t = tid; t < d / 2; t += 256) {
       const int64_t lo = ((t >> bit) << (bit + 1)) | (t & (((int64_t)1 << bit) - 1));
       const int64_t hi = lo | ((int64_t)1 << bit);

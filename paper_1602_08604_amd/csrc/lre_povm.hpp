@@ -20,7 +20,7 @@ namespace lre {
 
 // M from G (row-major 4 x 4) by Gauss-Jordan elimination with partial pivoting on
 // G^T G in binary64; a (nearly) singular G^T G raises FLAG_ARG and leaves M = 0.
-// Also clears the 64-bit total N that povm_total_kernel accumulates.
+// Also clears the 64-bit total N that the first pass accumulates.
 static __global__ void povm_setup_kernel(const double* __restrict__ G, double* __restrict__ M,
                                          unsigned long long* __restrict__ total, uint32_t* __restrict__ flags) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -63,20 +63,8 @@ static __global__ void povm_setup_kernel(const double* __restrict__ G, double* _
   if (!ok) atomicOr(flags, (uint32_t)FLAG_ARG);
 }
 
-// N = sum of all counts (grid-stride, one 64-bit atomic per block).
-static __global__ __launch_bounds__(256) void povm_total_kernel(const uint16_t* __restrict__ counts, int64_t count,
-                                                                unsigned long long* __restrict__ total) {
-  uint64_t s = 0;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (int64_t)gridDim.x * 256) s += counts[i];
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-  __shared__ uint64_t part[4];
-  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) atomicAdd(total, (unsigned long long)(part[0] + part[1] + part[2] + part[3]));
-}
-
-// Empty data (N = 0) is an error, as an empty basis is for the Pauli measurements.
+// Empty data (N = 0) is an error, as an empty basis is for the Pauli measurements
+// (checked after the first pass has summed the counts).
 static __global__ void povm_check_kernel(const unsigned long long* __restrict__ total, uint32_t* __restrict__ flags) {
   if (threadIdx.x == 0 && blockIdx.x == 0 && *total == 0ull) atomicOr(flags, (uint32_t)FLAG_EMPTY);
 }
@@ -114,19 +102,48 @@ __device__ __forceinline__ int povm_pad(int i) { return i + (i >> 4); }
 
 // First pass: a tile of 4^J consecutive counts (the J lowest digits) in LDS, the J
 // digits transformed two at a time in registers (one at a time for an odd J), then
-// written to coef -- divided by N when J = n (the only pass).
-
+// written to coef.  The tile's counts are summed on the way in: with J < n the block
+// adds its sum to N (the last pass divides); with J = n (one block, the only pass) its
+// sum is N and the block divides.
 template <int J, bool FINAL>
 __global__ __launch_bounds__(256) void povm_low_kernel(const uint16_t* __restrict__ counts, double* __restrict__ coef,
                                                        const double* __restrict__ M,
-                                                       const unsigned long long* __restrict__ total) {
+                                                       unsigned long long* __restrict__ total,
+                                                       uint32_t* __restrict__ flags) {
   constexpr int T = 1 << (2 * J);
   __shared__ double tile[T + T / 16 + 1];
+  __shared__ uint64_t part[4];
   double m[16];
   povm_load_m(M, m);
   const int64_t base = (int64_t)blockIdx.x * T;
-  for (int i = threadIdx.x; i < T; i += 256) tile[povm_pad(i)] = (double)counts[base + i];
+  uint64_t sum = 0;
+  if constexpr (T >= 8 * 256) {
+    // 16-byte loads: 8 counts per thread and step
+    for (int i = threadIdx.x * 8; i < T; i += 256 * 8) {
+      const uint4 u = *reinterpret_cast<const uint4*>(counts + base + i);
+      const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t lo = w[k] & 0xFFFFu, hi = w[k] >> 16;
+        tile[povm_pad(i + 2 * k)] = (double)lo;
+        tile[povm_pad(i + 2 * k + 1)] = (double)hi;
+        sum += lo + hi;
+      }
+    }
+  } else {
+    for (int i = threadIdx.x; i < T; i += 256) {
+      const uint32_t c = counts[base + i];
+      tile[povm_pad(i)] = (double)c;
+      sum += c;
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = sum;
   __syncthreads();
+  const uint64_t bsum = part[0] + part[1] + part[2] + part[3];
+  if (!FINAL && threadIdx.x == 0) atomicAdd(total, (unsigned long long)bsum);
+  if (FINAL && threadIdx.x == 0 && bsum == 0) atomicOr(flags, (uint32_t)FLAG_EMPTY);
 #pragma unroll
   for (int d = 0; d < J; d += 2) {
     const int nd = (J - d) >= 2 ? 2 : 1;          // digits in this stage
@@ -154,19 +171,22 @@ __global__ __launch_bounds__(256) void povm_low_kernel(const uint16_t* __restric
     }
     __syncthreads();
   }
-  const double N = FINAL ? (double)*total : 1.0;
+  const double N = (double)bsum;
   for (int i = threadIdx.x; i < T; i += 256) coef[base + i] = FINAL ? tile[povm_pad(i)] / N : tile[povm_pad(i)];
 }
 
-// Four digits lo .. lo + 3 (lo >= 3) of the vector, in place: a block holds 64
-// consecutive low indices (columns) x the 256 values of the four digits in LDS,
-// transforms them two digits at a time in registers; FINAL divides by N.
-constexpr int kPovmCols = 64;
+// Four digits lo .. lo + 3 (lo >= 3) of the vector, in place: a block holds 32
+// consecutive low indices (columns) x the 256 values of the four digits in LDS (64 KiB,
+// two blocks per compute unit), transforms them two digits at a time in registers;
+// FINAL divides by N.
+constexpr int kPovmCols = 32;
+constexpr int kPovmHighThreads = 512;
 
 template <bool FINAL>
-__global__ __launch_bounds__(256) void povm_high4_kernel(double* __restrict__ coef, int n, int lo,
-                                                         const double* __restrict__ M,
-                                                         const unsigned long long* __restrict__ total) {
+__global__ __launch_bounds__(kPovmHighThreads) void povm_high4_kernel(double* __restrict__ coef, int n, int lo,
+                                                                      const double* __restrict__ M,
+                                                                      const unsigned long long* __restrict__ total) {
+  constexpr int TH = kPovmHighThreads, RPP = TH / kPovmCols;   // rows of 256 loaded per pass
   __shared__ double blk[256 * kPovmCols];
   double m[16];
   povm_load_m(M, m);
@@ -175,13 +195,17 @@ __global__ __launch_bounds__(256) void povm_high4_kernel(double* __restrict__ co
   const int64_t hi = blockIdx.x / colgroups;
   const int64_t c0 = (blockIdx.x % colgroups) * kPovmCols;
   double* __restrict__ base = coef + hi * (L << 8) + c0;
-  const int col = threadIdx.x % kPovmCols, r0 = threadIdx.x / kPovmCols;   // 4 rows per pass
-  for (int d = r0; d < 256; d += 4) blk[d * kPovmCols + col] = base[(int64_t)d * L + col];
+  const int col = threadIdx.x % kPovmCols, r0 = threadIdx.x / kPovmCols;
+  double v[256 / RPP];
+#pragma unroll
+  for (int k = 0; k < 256 / RPP; ++k) v[k] = base[(int64_t)(r0 + RPP * k) * L + col];
+#pragma unroll
+  for (int k = 0; k < 256 / RPP; ++k) blk[(r0 + RPP * k) * kPovmCols + col] = v[k];
   __syncthreads();
 #pragma unroll
   for (int stage = 0; stage < 2; ++stage) {
-    // units: (column, the other two digits) = 64 x 16; 4 per thread
-    for (int u = threadIdx.x; u < kPovmCols * 16; u += 256) {
+    // units: (column, the other two digits) = 32 x 16, one per thread
+    for (int u = threadIdx.x; u < kPovmCols * 16; u += TH) {
       const int c = u % kPovmCols, other = u / kPovmCols;
       double y[16];
 #pragma unroll
@@ -199,8 +223,11 @@ __global__ __launch_bounds__(256) void povm_high4_kernel(double* __restrict__ co
     __syncthreads();
   }
   const double N = FINAL ? (double)*total : 1.0;
-  for (int d = r0; d < 256; d += 4)
+#pragma unroll
+  for (int k = 0; k < 256 / RPP; ++k) {
+    const int d = r0 + RPP * k;
     base[(int64_t)d * L + col] = FINAL ? blk[d * kPovmCols + col] / N : blk[d * kPovmCols + col];
+  }
 }
 
 // F <= 3 digits lo .. lo + F - 1 in registers, one thread per column (every other

@@ -122,6 +122,36 @@ def test_signed_sums_bit_exact(n):
     np.testing.assert_array_equal(S[:, ms].ravel(), ref)
 
 
+@pytest.mark.parametrize("n", [6, 7, 9, 11])
+def test_signed_sums_mfma_bit_exact(n):
+    """lre_signed_sums through the int8-MFMA 64-outcome transform of the MFMA counts pass:
+    equal to the plain sums and to the oracle; counts up to 65535 (both byte limbs)."""
+    print(f"[signed_sums MFMA n={n}]", flush=True)
+    rng = np.random.default_rng(90 + n)
+    if n <= 9:
+        counts = _haar_counts(n, 500, 60 + n)
+        counts[:3] = rng.integers(0, 65536, size=(3, 2 ** n))          # full uint16 range
+    else:
+        counts = rng.integers(0, 13, size=(3 ** n, 2 ** n), dtype=np.uint16)
+    bases = np.unique(np.concatenate([[0, 1, 2, 3 ** n - 1], rng.integers(0, 3 ** n, 24)]))
+    c, b = _dev(counts), _dev(bases.astype(np.int64))
+    S_m = L.signed_sums(c, b, flags=L.LRE_WHT_MFMA).cpu().numpy()
+    S_p = L.signed_sums(c, b).cpu().numpy()
+    np.testing.assert_array_equal(S_m, S_p)
+    ms = np.arange(2 ** n) if n <= 7 else rng.integers(0, 2 ** n, 300)
+    bb = np.repeat(bases, len(ms))
+    mm = np.tile(ms, len(bases))
+    ii = np.array([_walsh_coef_index(n, int(x), int(m)) for x, m in zip(bb, mm)])
+    np.testing.assert_array_equal(S_m[:, ms].ravel(), oracle.basis_sums(n, counts, bb, ii))
+
+
+def test_signed_sums_mfma_small_n_unsupported():
+    counts = _dev(_haar_counts(5, 100, 7))
+    with pytest.raises(L.LreError) as e:
+        L.signed_sums(counts, _dev(np.array([0, 1], dtype=np.int64)), flags=L.LRE_WHT_MFMA)
+    assert e.value.status == L.LRE_E_UNSUPPORTED
+
+
 @pytest.mark.parametrize("n", [3, 8, 10])
 def test_maximally_mixed_exact(n):
     """Equal counts: every non-identity coefficient is exactly 0 and rho = I / 2^n."""
