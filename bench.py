@@ -491,9 +491,16 @@ def bench_batch(args, torch, lre):
     ns, shots, counts = batch_instances(torch)
     torch.cuda.synchronize()
     t_gen = time.time() - t0
-    b = lre.Batch(counts, shots)
+    bflags = lre.LRE_NO_RHO if args.no_rho else 0
+    b = lre.Batch(counts, shots, flags=bflags)
     t0 = time.time()
-    tuned_ms = b.tune(reps=3)
+    if args.batch_tiles:
+        # a fixed work-item shape (e.g. the one the tuner chose in an earlier run), so that
+        # a profile of this run holds the timed launches only
+        b.set_tiles(*[int(v) for v in args.batch_tiles.split(",")])
+        tuned_ms = None
+    else:
+        tuned_ms = b.tune(reps=3)
     t_tune = time.time() - t0
     tiles = b.tiles
     b.run(check=True)
@@ -523,16 +530,24 @@ def bench_batch(args, torch, lre):
     ms_step = (t1 - t0) * 1e3 / args.steps
     ms_dev = e0.elapsed_time(e1) / args.steps
     n_counts = sum(3 ** n * 2 ** n for n in ns)
-    algo = sum(2.0 * 6 ** n + 8.0 * 4 ** n + 16.0 * 4 ** n for n in ns)
+    algo = sum(2.0 * 6 ** n + 8.0 * 4 ** n + (0.0 if args.no_rho else 16.0 * 4 ** n) for n in ns)
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     # FP32 rho error against FP64 over all instances
-    b32 = lre.Batch(counts, shots, flags=lre.LRE_RHO_FP32)
-    b32.run(check=True)
-    err_abs, err_fro = 0.0, 0.0
-    for r32, r64 in zip(b32.rhos, b.rhos):
-        dlt = r32.to(torch.complex128) - r64
-        err_abs = max(err_abs, dlt.abs().max().item())
-        err_fro = max(err_fro, (torch.linalg.norm(dlt) / torch.linalg.norm(r64)).item())
-    b32.close()
+    err_abs, err_fro = None, None
+    if not args.no_compare and not args.no_rho:
+        b32 = lre.Batch(counts, shots, flags=lre.LRE_RHO_FP32)
+        b32.run(check=True)
+        err_abs, err_fro = 0.0, 0.0
+        for r32, r64 in zip(b32.rhos, b.rhos):
+            dlt = r32.to(torch.complex128) - r64
+            err_abs = max(err_abs, dlt.abs().max().item())
+            err_fro = max(err_fro, (torch.linalg.norm(dlt) / torch.linalg.norm(r64)).item())
+        b32.close()
     print(f"[bench] batch: generated in {t_gen:.1f} s, tuned in {t_tune:.2f} s -> {tiles}; "
           f"{args.steps} replays: {ms_step:.3f} ms/step wall, {ms_dev:.3f} ms/step device", file=sys.stderr, flush=True)
     from collections import Counter
@@ -546,7 +561,8 @@ def bench_batch(args, torch, lre):
         "dtype": "int32+f64", "data": "synthetic",
         "config": {"workload": "batched: 512 instances, n uniform in {3..9} (default_rng(16042)), Haar pure "
                                "states, shots uniform in [100, 10^4], uint16 counts; one captured launch "
-                               "(counter fill + persistent kernel) per step",
+                               "(counter fill + persistent kernel) per step"
+                               + ("; coefficients only (no rho)" if args.no_rho else ""),
                    "instances": 512, "n_histogram": hist, "total_counts": n_counts, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": 2.0 * n_counts / (ms_dev / 1e3) / 1e9, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": 2.0 * n_counts / (ms_dev / 1e3) / 1e9 / HBM_PEAK_GBS,
@@ -590,6 +606,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="n14", choices=["n14", "n12", "n8", "batch", "project", "stream15", "povm14"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-tiles", default="",
+                    help="batch workload: workers_per_cu,counts_tiles,fold_cols,rho_blocks,interleave "
+                         "instead of running the autotuner")
+    ap.add_argument("--no-rho", action="store_true",
+                    help="batch workload: coefficients only (LRE_NO_RHO), to attribute step (ii)'s share")
     ap.add_argument("--no-n12", action="store_true",
                     help="n14 workload: skip the n = 12 sub-record")
     ap.add_argument("--project-n", type=int, default=12, choices=range(1, 15), metavar="N",

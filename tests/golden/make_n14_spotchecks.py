@@ -9,7 +9,8 @@ own per-group sum of Sec. III), then divided by (X^T X)_ii (Sec. III).  Entries 
 follow from eq. (4) on those coefficients (oracle.rho).
 
 Coefficients (all computed):
-  * i = 0 (all 3^14 bases), 6 of weight 1 (3^13 bases each), 20 of weight 2 (3^12 each);
+  * i = 0 (all 3^14 bases), 6 of weight 1 (3^13 bases each), 20 of weight 2 (3^12 each),
+    20 of weight 3 and 20 of weight 4;
   * 10^4 uniform on [1, 4^14);
   * for 5 nonzero patterns x (x_k = 1 where qubit k is off-diagonal; popcounts 14, 13,
     12, 11, 10), all 2^14 coefficients with letters in {X, Y} where x_k = 1 and {I, Z}
@@ -76,6 +77,15 @@ def main():
         letters[p1], letters[p2] = int(rng.integers(1, 4)), int(rng.integers(1, 4))
         w2.add(index_of(letters))
     groups["weight2"] = np.array(sorted(w2), dtype=np.int64)
+    for w in (3, 4):                       # 3^11 and 3^10 compatible bases each
+        ws = set()
+        while len(ws) < 20:
+            pos = rng.choice(N, size=w, replace=False)
+            letters = [0] * N
+            for p in pos:
+                letters[p] = int(rng.integers(1, 4))
+            ws.add(index_of(letters))
+        groups[f"weight{w}"] = np.array(sorted(ws), dtype=np.int64)
     groups["uniform"] = rng.integers(1, 4 ** N, size=10_000, dtype=np.int64)
     patterns = []
     for pc in (14, 13, 12, 11, 10):
