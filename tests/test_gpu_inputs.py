@@ -18,3 +18,7 @@ def test_philox_counts_match_twin(n, b0, nrows):
     ref = ti.philox_counts_rows(n, seed, np.arange(b0, b0 + nrows))
     np.testing.assert_array_equal(c, ref)
     np.testing.assert_array_equal(nb.cpu().numpy(), ref.sum(axis=1).astype(np.int64))
+    c, nb = gpu.philox_counts(n, seed, b0, nrows, paired=True)
+    ref, rnb = ti.philox_counts_rows_fast(n, seed, np.arange(b0, b0 + nrows), paired=True)
+    np.testing.assert_array_equal(c.cpu().numpy(), ref)
+    np.testing.assert_array_equal(nb.cpu().numpy(), rnb.astype(np.int64))

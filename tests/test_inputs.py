@@ -65,6 +65,13 @@ def test_philox_c_twin_matches_numpy_twin():
     ref = ti.philox_counts_rows(14, 987654321, bases)
     np.testing.assert_array_equal(c, ref)
     np.testing.assert_array_equal(nb, ref.sum(axis=1))
+    for n in (1, 3, 14):                       # paired rows: odd outcome = 12 - even one
+        b = bases[bases < 3 ** n]
+        c, nb = ti.philox_counts_rows_fast(n, 987654321, b, paired=True)
+        ref = ti.philox_counts_rows(n, 987654321, b).astype(np.int64)
+        np.testing.assert_array_equal(c[:, 0::2], ref[:, 0::2])
+        np.testing.assert_array_equal(c[:, 1::2], 12 - ref[:, 0::2])
+        assert np.all(nb == 12 << (n - 1))
 
 
 def test_device_rotated_amplitudes_match_numpy():

@@ -20,9 +20,10 @@ static uint32_t philox_x0(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, ui
   return c0;
 }
 
-/* Rows bases[0..nrows) into out[nrows][2^n]; totals into nb (may be NULL). */
-int tomo_philox_rows(int n, uint64_t seed, const int64_t* bases, int64_t nrows, uint16_t* out,
-                     uint32_t* nb) {
+/* Rows bases[0..nrows) into out[nrows][2^n]; totals into nb (may be NULL).  paired != 0:
+ * outcome 2k + 1 gets 12 minus the count of outcome 2k (uniform totals 12 * 2^(n-1)). */
+int tomo_philox_rows_mode(int n, uint64_t seed, const int64_t* bases, int64_t nrows, uint16_t* out,
+                          uint32_t* nb, int paired) {
   if (n < 1 || n > 20 || !bases || !out) return 1;
   const int64_t d = (int64_t)1 << n;
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
@@ -31,12 +32,22 @@ int tomo_philox_rows(int n, uint64_t seed, const int64_t* bases, int64_t nrows, 
     const uint64_t b = (uint64_t)bases[j];
     uint32_t sum = 0;
     for (int64_t s = 0; s < d; ++s) {
-      const uint32_t x = philox_x0((uint32_t)s, (uint32_t)b, (uint32_t)(b >> 32), 0u, k0, k1);
-      const uint32_t c = (uint32_t)(((uint64_t)x * 13u) >> 32);
+      uint32_t c;
+      if (paired && (s & 1)) {
+        c = 12u - out[j * d + s - 1];
+      } else {
+        const uint32_t x = philox_x0((uint32_t)s, (uint32_t)b, (uint32_t)(b >> 32), 0u, k0, k1);
+        c = (uint32_t)(((uint64_t)x * 13u) >> 32);
+      }
       out[j * d + s] = (uint16_t)c;
       sum += c;
     }
     if (nb) nb[j] = sum;
   }
   return 0;
+}
+
+int tomo_philox_rows(int n, uint64_t seed, const int64_t* bases, int64_t nrows, uint16_t* out,
+                     uint32_t* nb) {
+  return tomo_philox_rows_mode(n, seed, bases, nrows, out, nb, 0);
 }

@@ -21,23 +21,27 @@ def _load():
                                              ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                              ctypes.c_void_p]
         L.tomo_gen_philox_counts.restype = ctypes.c_int
+        L.tomo_gen_philox_counts_paired.argtypes = L.tomo_gen_philox_counts.argtypes
+        L.tomo_gen_philox_counts_paired.restype = ctypes.c_int
         _lib = L
     return _lib
 
 
 def philox_counts(n: int, seed: int, b_begin: int = 0, b_count: int | None = None,
                   counts: torch.Tensor | None = None, nb: torch.Tensor | None = None,
-                  device="cuda"):
+                  device="cuda", paired: bool = False):
     """Rows [b_begin, b_begin + b_count) of the Philox workload: (counts uint16 [rows, 2^n],
-    nb int32 [rows]), generated on the device."""
+    nb int32 [rows]), generated on the device.  paired: outcome 2k + 1 becomes 12 minus
+    outcome 2k, so every basis totals 12 * 2^(n-1) (a uniform-shot workload)."""
     b_count = 3 ** n - b_begin if b_count is None else b_count
     if counts is None:
         counts = torch.empty((b_count, 1 << n), dtype=torch.uint16, device=device)
     if nb is None:
         nb = torch.empty(b_count, dtype=torch.int32, device=device)
     st = torch.cuda.current_stream(counts.device).cuda_stream
-    rc = _load().tomo_gen_philox_counts(n, seed, b_begin, b_count, ctypes.c_void_p(counts.data_ptr()),
-                                        ctypes.c_void_p(nb.data_ptr()), ctypes.c_void_p(st))
+    gen = _load().tomo_gen_philox_counts_paired if paired else _load().tomo_gen_philox_counts
+    rc = gen(n, seed, b_begin, b_count, ctypes.c_void_p(counts.data_ptr()), ctypes.c_void_p(nb.data_ptr()),
+             ctypes.c_void_p(st))
     if rc != 0:
         raise RuntimeError(f"tomo_gen_philox_counts failed ({rc})")
     return counts, nb

@@ -64,22 +64,24 @@ def philox_counts_rows(n: int, seed: int, bases) -> np.ndarray:
 _clib = None
 
 
-def philox_counts_rows_fast(n: int, seed: int, bases) -> tuple[np.ndarray, np.ndarray]:
+def philox_counts_rows_fast(n: int, seed: int, bases, paired: bool = False) -> tuple[np.ndarray, np.ndarray]:
     """Same rows as philox_counts_rows, from the OpenMP C twin; also returns the row totals.
+    paired: outcome 2k + 1 becomes 12 minus outcome 2k (uniform totals 12 * 2^(n-1)).
     Builds the C twin on first use."""
     global _clib
     import ctypes
     if _clib is None:
         from .build import build_cpu
         L = ctypes.CDLL(build_cpu(force=False))
-        L.tomo_philox_rows.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_void_p,
-                                       ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]
-        L.tomo_philox_rows.restype = ctypes.c_int
+        L.tomo_philox_rows_mode.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_void_p,
+                                            ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
+        L.tomo_philox_rows_mode.restype = ctypes.c_int
         _clib = L
     b = np.ascontiguousarray(bases, dtype=np.int64)
     out = np.empty((len(b), 2 ** n), dtype=np.uint16)
     nb = np.empty(len(b), dtype=np.uint32)
-    rc = _clib.tomo_philox_rows(n, seed, b.ctypes.data, len(b), out.ctypes.data, nb.ctypes.data)
+    rc = _clib.tomo_philox_rows_mode(n, seed, b.ctypes.data, len(b), out.ctypes.data, nb.ctypes.data,
+                                     1 if paired else 0)
     if rc:
         raise RuntimeError("tomo_philox_rows failed")
     return out, nb
