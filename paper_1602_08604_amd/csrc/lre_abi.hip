@@ -34,7 +34,6 @@ constexpr int kMaxFLast = 2;  // qubits folded by the final pass (below kMinHF4)
 constexpr int kMinHF4 = 5;    // from this many unfolded qubits on, the first later pass
                               // folds 4 with LDS accumulators and the final one the rest
 constexpr int kRhoJ = 6;      // qubits of the low step-(ii) transform
-constexpr int kRhoRegH = 4;   // high step-(ii) qubits transformed in registers (n <= 10)
 
 enum class Ty : int { U32 = 0, F64 = 1 };
 
@@ -375,23 +374,21 @@ void launch_rho(const Plan& P, const double* coef, void* rho, char* ws, hipStrea
     }
     return;
   }
+  if (n - kRhoJ <= 4) {
+    // up to 4 high qubits: units (x_hi, 8 x_lo) from coefficients to mu in LDS
+    const dim3 grid((unsigned)((int64_t)8 << (n - kRhoJ)));
+    switch (n - kRhoJ) {
+      case 1: hipLaunchKernelGGL((rho_tile_kernel<1, OutT>), grid, dim3(512), 0, st, coef, rho); break;
+      case 2: hipLaunchKernelGGL((rho_tile_kernel<2, OutT>), grid, dim3(512), 0, st, coef, rho); break;
+      case 3: hipLaunchKernelGGL((rho_tile_kernel<3, OutT>), grid, dim3(512), 0, st, coef, rho); break;
+      default: hipLaunchKernelGGL((rho_tile_kernel<4, OutT>), grid, dim3(512), 0, st, coef, rho); break;
+    }
+    return;
+  }
   double2* tmp = reinterpret_cast<double2*>(ws + P.off_tmp);
   const int64_t nblk = ipow4(n - kRhoJ);
   const int64_t low_blocks = std::min<int64_t>(nblk, resident_blocks(rho_low6_kernel, 256, 4096 * 8));
   hipLaunchKernelGGL(rho_low6_kernel, dim3((unsigned)low_blocks), dim3(256), 0, st, coef, tmp, nblk);
-  const int64_t D = (int64_t)1 << kRhoJ;
-  if (n - kRhoJ <= kRhoRegH) {
-    // few high qubits: one thread per (x_hi, r_lo, x_lo), transform in registers
-    const int64_t count = ((int64_t)1 << (n - kRhoJ)) * D * D;
-    const dim3 grid((unsigned)((count + 255) / 256));
-    switch (n - kRhoJ) {
-      case 1: hipLaunchKernelGGL((rho_high_reg_kernel<1, OutT>), grid, dim3(256), 0, st, (const double2*)tmp, rho, n, (int)kRhoJ, count); break;
-      case 2: hipLaunchKernelGGL((rho_high_reg_kernel<2, OutT>), grid, dim3(256), 0, st, (const double2*)tmp, rho, n, (int)kRhoJ, count); break;
-      case 3: hipLaunchKernelGGL((rho_high_reg_kernel<3, OutT>), grid, dim3(256), 0, st, (const double2*)tmp, rho, n, (int)kRhoJ, count); break;
-      default: hipLaunchKernelGGL((rho_high_reg_kernel<4, OutT>), grid, dim3(256), 0, st, (const double2*)tmp, rho, n, (int)kRhoJ, count); break;
-    }
-    return;
-  }
   // 5..9 high qubits: two register phases with one LDS transpose
   switch (n - kRhoJ) {
     case 5: launch_rho_high2<5, OutT>(tmp, rho, n, st); break;

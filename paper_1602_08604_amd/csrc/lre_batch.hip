@@ -58,7 +58,7 @@ struct BInst {
   void* rho;
   const uint32_t* nb_in;      // caller's per-basis totals (per-basis mode) or NULL
   uint64_t shots;             // 0: per-basis totals
-  int64_t off_part, off_tmp;  // workspace offsets
+  int64_t off_part;           // workspace offset of the later-pass partials
   int64_t off_nb, off_inv;    // per-basis mode: N_b and 1/N_b in the workspace
   int32_t n, q1;
 };
@@ -68,16 +68,25 @@ struct BInst {
 // flat loads, which also count against the LDS wait counter and turn every wait in the
 // prefetching loops into a full wait).
 #define LRE_GLOBAL __attribute__((address_space(1)))
+// The workgroup's LDS buffer is handed to the (not inlined) item functions typed in the
+// LDS address space: as a generic pointer it compiled to a flat-to-LDS conversion with a
+// null check before every LDS access of the counts pass.
+#define LRE_LDS __attribute__((address_space(3)))
 
 struct BInstG {
   const LRE_GLOBAL uint16_t* counts;
   LRE_GLOBAL double* coef;
   LRE_GLOBAL char* rho;
-  const LRE_GLOBAL uint32_t* nb_in;
   uint64_t shots;
-  int64_t off_part, off_tmp;
-  int64_t off_nb, off_inv;
+  int64_t off_part;
   int32_t n, q1;
+};
+
+// The per-basis fields, apart, so that the view every item takes (and the stack frame of
+// the uniform-shot item functions) stays small.
+struct BInstPB {
+  const LRE_GLOBAL uint32_t* nb_in;
+  int64_t off_nb, off_inv;
 };
 
 __device__ __forceinline__ BInstG global_view(const BInst& I) {
@@ -85,93 +94,79 @@ __device__ __forceinline__ BInstG global_view(const BInst& I) {
   G.counts = (const LRE_GLOBAL uint16_t*)I.counts;
   G.coef = (LRE_GLOBAL double*)I.coef;
   G.rho = (LRE_GLOBAL char*)I.rho;
-  G.nb_in = (const LRE_GLOBAL uint32_t*)I.nb_in;
   G.shots = I.shots;
   G.off_part = I.off_part;
-  G.off_tmp = I.off_tmp;
-  G.off_nb = I.off_nb;
-  G.off_inv = I.off_inv;
   G.n = I.n;
   G.q1 = I.q1;
   return G;
+}
+
+__device__ __forceinline__ BInstPB pb_view(const BInst& I) {
+  BInstPB X;
+  X.nb_in = (const LRE_GLOBAL uint32_t*)I.nb_in;
+  X.off_nb = I.off_nb;
+  X.off_inv = I.off_inv;
+  return X;
 }
 
 constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
 constexpr size_t kLdsCounts = (size_t)StreamGeom<kQ>::NACC * 4 + (size_t)StreamGeom<kQ>::NROWS * 4;
 constexpr size_t kLdsRhoLow = 2 * (size_t)RhoLowLds<kJ>::SIZE * 8;
 constexpr size_t kLds = cmax(kLdsCounts, kLdsRhoLow);
+static_assert(RhoTileGeom<3>::NV * sizeof(double) <= kLds, "step-(ii) units of n = 9 fit the LDS buffer");
 // per-basis plans: binary64 accumulators (one workgroup per CU)
 constexpr size_t kLdsCountsPB = (size_t)StreamGeom<kQ>::NACC * 8 + (size_t)StreamGeom<kQ>::NROWS * 4;
 constexpr size_t kLdsPB = cmax(kLdsCountsPB, kLdsRhoLow);
-constexpr int64_t kRhoElemsPerBlock = 4096;  // step-(ii) high elements per unit of rho_blocks
 
 // The callees below take the instance with global-typed pointers; the generic pointers
 // they hand to the shared device functions are casts of them, from which the compiler
 // infers global loads and stores.
 __device__ __forceinline__ char* g2p(LRE_GLOBAL char* p) { return (char*)p; }
-
-template <int H, typename OutT>
-__device__ __forceinline__ void rho_high_loop(const double2* tmp, void* rho, int n, int64_t e0, int64_t e1, int tid) {
-#pragma unroll 4
-  for (int64_t t = e0 + tid; t < e1; t += kBT) rho_high_reg<H, OutT>(tmp, rho, n, kJ, t);
-}
-
-template <typename OutT>
-__device__ __forceinline__ void rho_high_range(const BInstG& I, int64_t e0, int64_t e1, int tid, LRE_GLOBAL char* ws) {
-  const double2* tmp = reinterpret_cast<const double2*>(g2p(ws + I.off_tmp));
-  void* rho = (void*)g2p(I.rho);
-  switch (I.n - kJ) {
-    case 1: rho_high_loop<1, OutT>(tmp, rho, I.n, e0, e1, tid); break;
-    case 2: rho_high_loop<2, OutT>(tmp, rho, I.n, e0, e1, tid); break;
-    default: rho_high_loop<3, OutT>(tmp, rho, I.n, e0, e1, tid); break;
-  }
-}
+template <typename T>
+__device__ __forceinline__ T* l2p(LRE_LDS char* p) { return (T*)p; }
 
 // An instance with n <= 7 (one counts-pass tile) from counts to rho in one workgroup;
 // __syncthreads orders the phases (it is a workgroup-scope release/acquire).
 template <int Q, typename OutT>
-__device__ __forceinline__ void small_rho(const BInstG& I, int tid, LRE_GLOBAL char* ws, double* re, double* im) {
+__device__ __forceinline__ void small_rho(const BInstG& I, int tid, double* re, double* im) {
   const double* coef = (const double*)I.coef;
   if constexpr (Q <= kJ) {
     rho_low_block<Q, true, OutT, kBT>(coef, (void*)g2p(I.rho), I.n, 0, tid, re, im);
   } else {
-    rho_low6_blocks<kBT>(coef, reinterpret_cast<double2*>(g2p(ws + I.off_tmp)), [](int z) { return (int64_t)z; },
-                         4, tid, re);
-    __syncthreads();
-    rho_high_range<OutT>(I, 0, (int64_t)2 * 64 * 64, tid, ws);
+    rho_tiles<Q - kJ, OutT, kBT>(coef, (void*)g2p(I.rho), 0, (int64_t)8 << (Q - kJ), tid, re);
   }
 }
 
 template <int Q, bool MAD24, bool PREFETCH>
-__device__ __noinline__ void run_small(const BInstG& I, uint8_t var, int tid, LRE_GLOBAL char* ws, char* smem,
+__device__ __noinline__ void run_small(const BInstG& I, uint8_t var, int tid, LRE_GLOBAL char* ws, LRE_LDS char* smem,
                                        uint32_t* flags) {
-  uint32_t* acc = reinterpret_cast<uint32_t*>(smem);
+  uint32_t* acc = l2p<uint32_t>(smem);
   uint32_t* rs = acc + StreamGeom<Q>::NACC;
   counts_block<Q, kBT, uint32_t, false, Out::CoefUniform, MAD24, PREFETCH>(
       (const uint16_t*)I.counts, I.n, 1, nullptr, (void*)(double*)I.coef, nullptr, I.shots, 0, tid, acc, rs, flags);
   __syncthreads();
   if (var & V_RHO) {
-    double* re = reinterpret_cast<double*>(smem);
+    double* re = l2p<double>(smem);
     double* im = re + (kLds / 16);
-    if (var & V_FP32) small_rho<Q, float>(I, tid, ws, re, im);
-    else small_rho<Q, double>(I, tid, ws, re, im);
+    if (var & V_FP32) small_rho<Q, float>(I, tid, re, im);
+    else small_rho<Q, double>(I, tid, re, im);
   }
 }
 
 // Per-basis totals of bases [b0, b1) (Sec. II eq. 3 frequencies p = c / N_b): N_b, the
 // caller's or else the row sum, into the workspace, 1/N_b (correctly rounded) beside
 // it, FLAG_EMPTY for an empty basis.  A group of 16 lanes per basis row.
-__device__ __noinline__ void run_totals(const BInstG& I, int64_t b0, int64_t b1, int tid, LRE_GLOBAL char* ws,
-                                        uint32_t* flags) {
-  LRE_GLOBAL uint32_t* nb = (LRE_GLOBAL uint32_t*)(ws + I.off_nb);
-  LRE_GLOBAL double* inv = (LRE_GLOBAL double*)(ws + I.off_inv);
+__device__ __noinline__ void run_totals(const BInstG& I, const BInstPB& X, int64_t b0, int64_t b1, int tid,
+                                        LRE_GLOBAL char* ws, uint32_t* flags) {
+  LRE_GLOBAL uint32_t* nb = (LRE_GLOBAL uint32_t*)(ws + X.off_nb);
+  LRE_GLOBAL double* inv = (LRE_GLOBAL double*)(ws + X.off_inv);
   constexpr int kGroups = kBT / 16;
   const int grp = tid / 16, lam = tid % 16;
   const int64_t d = (int64_t)1 << I.n;
   for (int64_t b = b0 + grp; b < b1; b += kGroups) {   // uniform within a group
     uint32_t N;
-    if (I.nb_in) {
-      N = I.nb_in[b];
+    if (X.nb_in) {
+      N = X.nb_in[b];
     } else {
       uint32_t sum = 0;
       for (int64_t o = lam; o < d; o += 16) sum += I.counts[b * d + o];
@@ -190,33 +185,33 @@ __device__ __noinline__ void run_totals(const BInstG& I, int64_t b0, int64_t b1,
 // A per-basis instance with n <= 7 in one workgroup: totals, counts pass with binary64
 // accumulators (row totals checked against N_b), step (ii).
 template <int Q, bool PREFETCH>
-__device__ __noinline__ void run_small_pb(const BInstG& I, uint8_t var, int tid, LRE_GLOBAL char* ws, char* smem,
-                                          uint32_t* flags) {
-  run_totals(I, 0, ipow3(I.n), tid, ws, flags);
+__device__ __noinline__ void run_small_pb(const BInstG& I, const BInstPB& X, uint8_t var, int tid, LRE_GLOBAL char* ws,
+                                          LRE_LDS char* smem, uint32_t* flags) {
+  run_totals(I, X, 0, ipow3(I.n), tid, ws, flags);
   __syncthreads();  // workgroup scope: the totals written above are visible to the block
-  double* acc = reinterpret_cast<double*>(smem);
+  double* acc = l2p<double>(smem);
   uint32_t* rs = reinterpret_cast<uint32_t*>(acc + StreamGeom<Q>::NACC);
   counts_block<Q, kBT, double, true, Out::CoefPerBasis, false, PREFETCH>(
-      (const uint16_t*)I.counts, I.n, 1, (const double*)g2p(ws + I.off_inv), (void*)(double*)I.coef, nullptr, 0, 0,
-      tid, acc, rs, flags, (const uint32_t*)g2p(ws + I.off_nb));
+      (const uint16_t*)I.counts, I.n, 1, (const double*)g2p(ws + X.off_inv), (void*)(double*)I.coef, nullptr, 0, 0,
+      tid, acc, rs, flags, (const uint32_t*)g2p(ws + X.off_nb));
   __syncthreads();
   if (var & V_RHO) {
-    double* re = reinterpret_cast<double*>(smem);
+    double* re = l2p<double>(smem);
     double* im = re + (kLds / 16);
-    if (var & V_FP32) small_rho<Q, float>(I, tid, ws, re, im);
-    else small_rho<Q, double>(I, tid, ws, re, im);
+    if (var & V_FP32) small_rho<Q, float>(I, tid, re, im);
+    else small_rho<Q, double>(I, tid, re, im);
   }
 }
 
 // Per-basis counts-pass row groups [g0, g1): binary64 partials, rows checked against N_b.
 template <bool PREFETCH>
-__device__ __noinline__ void run_counts_pb(const BInstG& I, int64_t g0, int64_t g1, int tid, LRE_GLOBAL char* ws,
-                                           char* smem, uint32_t* flags) {
-  double* acc = reinterpret_cast<double*>(smem);
+__device__ __noinline__ void run_counts_pb(const BInstG& I, const BInstPB& X, int64_t g0, int64_t g1, int tid,
+                                           LRE_GLOBAL char* ws, LRE_LDS char* smem, uint32_t* flags) {
+  double* acc = l2p<double>(smem);
   uint32_t* rs = reinterpret_cast<uint32_t*>(acc + StreamGeom<kQ>::NACC);
   void* part = (void*)g2p(ws + I.off_part);
-  const double* inv = (const double*)g2p(ws + I.off_inv);
-  const uint32_t* nb = (const uint32_t*)g2p(ws + I.off_nb);
+  const double* inv = (const double*)g2p(ws + X.off_inv);
+  const uint32_t* nb = (const uint32_t*)g2p(ws + X.off_nb);
   const uint16_t* counts = (const uint16_t*)I.counts;
   const int chunks = 1 << (I.n - kQ);
   for (int64_t g = g0; g < g1; ++g) {
@@ -230,8 +225,8 @@ __device__ __noinline__ void run_counts_pb(const BInstG& I, int64_t g0, int64_t 
 // outcome tiles of its rows, so the row totals are complete and checked in the block.
 template <bool MAD24, bool PREFETCH>
 __device__ __noinline__ void run_counts(const BInstG& I, int64_t g0, int64_t g1, int tid, LRE_GLOBAL char* ws,
-                                        char* smem, uint32_t* flags) {
-  uint32_t* acc = reinterpret_cast<uint32_t*>(smem);
+                                        LRE_LDS char* smem, uint32_t* flags) {
+  uint32_t* acc = l2p<uint32_t>(smem);
   uint32_t* rs = acc + StreamGeom<kQ>::NACC;
   void* part = (void*)g2p(ws + I.off_part);
   const uint16_t* counts = (const uint16_t*)I.counts;
@@ -290,35 +285,20 @@ __device__ __noinline__ void run_fold_pb(const BInstG& I, int64_t c0, int64_t c1
   else fold_cols<2, double, Out::CoefPerBasis>(in, coef, I.n, 0, c0, c1, tid);
 }
 
-// Step (ii) for the x_hi values [x0, x1) of an instance with n > 7: the low transform of
-// the 2^H coefficient blocks whose high letters have pattern x_hi (into the
-// intermediate), then the high transform of the 4^6 (r_lo, x_lo) entries of each x_hi
-// row group -- both inside this workgroup, ordered by barriers.
+// Step (ii) for the high patterns x_hi in [x0, x1) of an instance with n = 8 or 9: the
+// units (x_hi, xb) of those patterns in sequence, each from coefficients to mu inside
+// this workgroup (no intermediate in device memory).
 template <typename OutT>
-__device__ __noinline__ void run_rho(const BInstG& I, int64_t x0, int64_t x1, int tid, LRE_GLOBAL char* ws,
-                                     char* smem) {
-  double* re = reinterpret_cast<double*>(smem);
+__device__ __noinline__ void run_rho(const BInstG& I, int64_t x0, int64_t x1, int tid, LRE_LDS char* smem) {
+  double* V = l2p<double>(smem);
   const double* coef = (const double*)I.coef;
-  double2* tmp = reinterpret_cast<double2*>(g2p(ws + I.off_tmp));
-  const int H = I.n - kJ;
-  for (int64_t xh = x0; xh < x1; ++xh) {
-    auto a_of = [&](int z) {
-      int64_t a_hi = 0;
-      for (int p = H - 1; p >= 0; --p) {
-        const int xb = (int)(xh >> p) & 1, zb = (z >> p) & 1;
-        a_hi = a_hi * 4 + (xb ? (zb ? 2 : 1) : (zb ? 3 : 0));
-      }
-      return a_hi;
-    };
-    rho_low6_blocks<kBT>(coef, tmp, a_of, 1 << H, tid, re);
-    __syncthreads();
-    rho_high_range<OutT>(I, xh * kRhoElemsPerBlock, (xh + 1) * kRhoElemsPerBlock, tid, ws);
-    __syncthreads();
-  }
+  void* rho = (void*)g2p(I.rho);
+  if (I.n == kJ + 2) rho_tiles<2, OutT, kBT>(coef, rho, x0 * 8, x1 * 8, tid, V);
+  else rho_tiles<3, OutT, kBT>(coef, rho, x0 * 8, x1 * 8, tid, V);
 }
 
 template <bool PREFETCH>
-__device__ __forceinline__ void dispatch_small(const BInstG& I, uint8_t var, int tid, LRE_GLOBAL char* ws, char* smem,
+__device__ __forceinline__ void dispatch_small(const BInstG& I, uint8_t var, int tid, LRE_GLOBAL char* ws, LRE_LDS char* smem,
                                                uint32_t* flags) {
   switch (I.n) {
     case 1: run_small<1, false, PREFETCH>(I, var, tid, ws, smem, flags); break;
@@ -335,16 +315,16 @@ __device__ __forceinline__ void dispatch_small(const BInstG& I, uint8_t var, int
 }
 
 template <bool PREFETCH>
-__device__ __forceinline__ void dispatch_small_pb(const BInstG& I, uint8_t var, int tid, LRE_GLOBAL char* ws,
-                                                  char* smem, uint32_t* flags) {
+__device__ __forceinline__ void dispatch_small_pb(const BInstG& I, const BInstPB& X, uint8_t var, int tid,
+                                                  LRE_GLOBAL char* ws, LRE_LDS char* smem, uint32_t* flags) {
   switch (I.n) {
-    case 1: run_small_pb<1, PREFETCH>(I, var, tid, ws, smem, flags); break;
-    case 2: run_small_pb<2, PREFETCH>(I, var, tid, ws, smem, flags); break;
-    case 3: run_small_pb<3, PREFETCH>(I, var, tid, ws, smem, flags); break;
-    case 4: run_small_pb<4, PREFETCH>(I, var, tid, ws, smem, flags); break;
-    case 5: run_small_pb<5, PREFETCH>(I, var, tid, ws, smem, flags); break;
-    case 6: run_small_pb<6, PREFETCH>(I, var, tid, ws, smem, flags); break;
-    default: run_small_pb<7, PREFETCH>(I, var, tid, ws, smem, flags); break;
+    case 1: run_small_pb<1, PREFETCH>(I, X, var, tid, ws, smem, flags); break;
+    case 2: run_small_pb<2, PREFETCH>(I, X, var, tid, ws, smem, flags); break;
+    case 3: run_small_pb<3, PREFETCH>(I, X, var, tid, ws, smem, flags); break;
+    case 4: run_small_pb<4, PREFETCH>(I, X, var, tid, ws, smem, flags); break;
+    case 5: run_small_pb<5, PREFETCH>(I, X, var, tid, ws, smem, flags); break;
+    case 6: run_small_pb<6, PREFETCH>(I, X, var, tid, ws, smem, flags); break;
+    default: run_small_pb<7, PREFETCH>(I, X, var, tid, ws, smem, flags); break;
   }
 }
 
@@ -360,7 +340,8 @@ __global__ __launch_bounds__(kBT, WORKERS == 2 ? 4 : 1) void batch_kernel(
     char* __restrict__ ws_arg, uint32_t* __restrict__ ctl, uint32_t* __restrict__ flags) {
   constexpr bool PF = WORKERS == 1;
   static_assert(!PB || WORKERS == 1, "per-basis plans run one workgroup per CU");
-  __shared__ __align__(16) char smem[PB ? kLdsPB : kLds];
+  __shared__ __align__(16) char smem_arr[PB ? kLdsPB : kLds];
+  LRE_LDS char* smem = (LRE_LDS char*)smem_arr;
   __shared__ int s_item;
   __shared__ int s_skip;
   const int tid = threadIdx.x;
@@ -399,7 +380,7 @@ __global__ __launch_bounds__(kBT, WORKERS == 2 ? 4 : 1) void batch_kernel(
       case K_SMALL:
         if constexpr (PB) {
           if (pb) {
-            dispatch_small_pb<PF>(I, W.variant, tid, ws, smem, flags);
+            dispatch_small_pb<PF>(I, pb_view(insts[W.inst]), W.variant, tid, ws, smem, flags);
             break;
           }
         }
@@ -408,7 +389,7 @@ __global__ __launch_bounds__(kBT, WORKERS == 2 ? 4 : 1) void batch_kernel(
       case K_COUNTS:
         if constexpr (PB) {
           if (pb) {
-            run_counts_pb<PF>(I, W.begin, W.end, tid, ws, smem, flags);
+            run_counts_pb<PF>(I, pb_view(insts[W.inst]), W.begin, W.end, tid, ws, smem, flags);
             break;
           }
         }
@@ -416,7 +397,7 @@ __global__ __launch_bounds__(kBT, WORKERS == 2 ? 4 : 1) void batch_kernel(
         else run_counts<false, PF>(I, W.begin, W.end, tid, ws, smem, flags);
         break;
       case K_TOTALS:
-        if constexpr (PB) run_totals(I, W.begin, W.end, tid, ws, flags);
+        if constexpr (PB) run_totals(I, pb_view(insts[W.inst]), W.begin, W.end, tid, ws, flags);
         break;
       case K_FOLD:
         if constexpr (PB) {
@@ -428,8 +409,8 @@ __global__ __launch_bounds__(kBT, WORKERS == 2 ? 4 : 1) void batch_kernel(
         run_fold(I, W.begin, W.end, tid, ws);
         break;
       default:
-        if (W.variant & V_FP32) run_rho<float>(I, W.begin, W.end, tid, ws, smem);
-        else run_rho<double>(I, W.begin, W.end, tid, ws, smem);
+        if (W.variant & V_FP32) run_rho<float>(I, W.begin, W.end, tid, smem);
+        else run_rho<double>(I, W.begin, W.end, tid, smem);
         break;
     }
     if (W.done_ctr >= 0) {
@@ -641,11 +622,6 @@ lre_status lre_batch_plan(lre_ctx* ctx, const lre_instance* inst, int count, uin
       off += align256((size_t)ipow3(I.n) * 4);
       d.off_inv = (int64_t)off;
       off += align256((size_t)ipow3(I.n) * 8);
-    }
-    d.off_tmp = 0;
-    if (want_rho && I.n > kJ) {
-      d.off_tmp = (int64_t)off;
-      off += align256((size_t)ipow4(I.n) * 16);
     }
   }
   B->ws_bytes = off;

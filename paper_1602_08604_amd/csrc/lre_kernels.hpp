@@ -31,10 +31,13 @@
 // transform over z in {0,1}^n of e_{a(x,z)} (-i)^{|x&z|}, where per qubit the pair
 // (x_k, z_k) = (0,0),(1,0),(1,1),(0,1) is the letter I, X, Y, Z (the paper's grouping of
 // the Omega_i by nonzero pattern, Sec. IV).  n <= 6: rho_low_kernel does all of it in
-// LDS.  n > 6: rho_low6_kernel transforms the low 6 qubits of each 4^6 coefficient
-// block (registers + lane quads), then rho_high_reg_kernel (up to 4 high qubits, in
-// registers) or rho_high2_kernel (5 to 8, two register phases and one LDS transpose)
-// the remaining high qubits, writing the row-major matrix.
+// LDS.  7 <= n <= 10: rho_tile_kernel, units of one high pattern and 8 low patterns
+// from coefficients to mu in LDS (a real low transform, the complex one rebuilt from
+// pairs of its outputs, the high transform in registers).  n > 10: rho_low6_kernel
+// transforms the low 6 qubits of each 4^6 coefficient block (registers + lane quads)
+// into a complex intermediate, then rho_high2_kernel (5 to 9 high qubits, two register
+// phases and one LDS transpose) the remaining high qubits, writing the row-major
+// matrix.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -1504,50 +1507,6 @@ __global__ __launch_bounds__(256) void rho_low_kernel(const double* __restrict__
   rho_low_block<J, FINAL, OutT, 256>(coef, out, n, blockIdx.x, threadIdx.x, re, im);
 }
 
-// High transform with H <= 4 high qubits in registers: one element t = (x_hi, r_lo, x_lo)
-// per call (x_lo fastest, so reads of tmp and writes of mu are coalesced); the 2^H
-// values over z_hi are transformed in registers and written to the 2^H rows r_hi.
-template <int H, typename OutT>
-__device__ __forceinline__ void rho_high_reg(const double2* __restrict__ tmp, void* __restrict__ rho, int n, int J,
-                                             int64_t t) {
-  constexpr int NH = 1 << H;
-  const int64_t D = (int64_t)1 << J;
-  const int64_t x_lo = t & (D - 1);
-  const int64_t r_lo = (t >> J) & (D - 1);
-  const int x_hi = (int)(t >> (2 * J));
-  double re[NH], im[NH];
-#pragma unroll
-  for (int z = 0; z < NH; ++z) {
-    int64_t a_hi = 0;
-#pragma unroll
-    for (int p = H - 1; p >= 0; --p) {
-      const int xb = (x_hi >> p) & 1, zb = (z >> p) & 1;
-      a_hi = a_hi * 4 + (xb ? (zb ? 2 : 1) : (zb ? 3 : 0));
-    }
-    const double2 v = tmp[(a_hi * D + r_lo) * D + x_lo];
-    re[z] = v.x;
-    im[z] = v.y;
-    mul_neg_i_pow(__popc((unsigned)(x_hi & z)), re[z], im[z]);
-  }
-  wht_regs<H>(re);
-  wht_regs<H>(im);
-  const double scale = ldexp(1.0, -n);
-  const int64_t dn = (int64_t)1 << n;
-#pragma unroll
-  for (int r_hi = 0; r_hi < NH; ++r_hi) {
-    const int64_t row = ((int64_t)r_hi << J) | r_lo;
-    const int64_t col = ((int64_t)(r_hi ^ x_hi) << J) | (r_lo ^ x_lo);
-    store_complex<OutT>(rho, row * dn + col, re[r_hi] * scale, im[r_hi] * scale);
-  }
-}
-
-template <int H, typename OutT>
-__global__ __launch_bounds__(256) void rho_high_reg_kernel(const double2* __restrict__ tmp, void* __restrict__ rho,
-                                                           int n, int J, int64_t count) {
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (t < count) rho_high_reg<H, OutT>(tmp, rho, n, J, t);
-}
-
 // Bit p of v moved to bit 2p (6 bits).
 __device__ __forceinline__ uint32_t spread6(uint32_t v) {
   uint32_t r = 0;
@@ -1633,6 +1592,134 @@ static __global__ __launch_bounds__(256) void rho_low6_kernel(const double* __re
   if (b0 >= nblk) return;
   const int nz = (int)((nblk - 1 - b0) / st + 1);
   rho_low6_blocks<256>(coef, tmp, [&](int z) { return b0 + (int64_t)z * st; }, nz, threadIdx.x, blk);
+}
+
+// Bit p of v moved to bit 2p (B bits).
+template <int B>
+__device__ __forceinline__ uint32_t spread_bits(uint32_t v) {
+  uint32_t r = 0;
+#pragma unroll
+  for (int p = 0; p < B; ++p) r |= ((v >> p) & 1u) << (2 * p);
+  return r;
+}
+
+// Letter code of B qubits with x bits x and z bits z (per qubit I, X, Y, Z for (x, z) =
+// (0,0), (1,0), (1,1), (0,1)), base-4 digits in the same order as the bits.
+template <int B>
+__device__ __forceinline__ uint32_t letters_of(uint32_t x, uint32_t z) {
+  const uint32_t sz = spread_bits<B>(z);
+  return spread_bits<B>(x) ^ sz ^ (sz << 1);
+}
+
+// Step (ii) for n = 6 + H <= 10 with no intermediate in device memory.  A unit is a high
+// pattern x_hi and 8 consecutive low patterns x_lo = 8 xb + j (unit index 8 x_hi + xb).
+// Its inputs are the coefficients of the 2^H blocks a_hi(x_hi, z_hi) whose letters on
+// low qubits 3..5 match xb: 2^H x 8 runs of 64 consecutive coefficients (the letters of
+// qubits 0..2 free), staged in LDS as V[z_hi][z_lo bits 3..5][letters of qubits 0..2].
+// The low transform is real: for each (z_hi, j),
+//   T(r_lo) = sum_{z_lo} e (-1)^{floor(|x_lo & z_lo| / 2)} (-1)^{z_lo . r_lo},
+// in place (each (j, z_lo) owns one slot; output r_lo goes to the slot of z_lo = r_lo).
+// Since (-i)^k = (-1)^{floor(k/2)} (-i)^{k mod 2} and k mod 2 = x_lo . z_lo is a
+// character, the complex low transform of e (-i)^{|x_lo & z_lo|} at r_lo is
+//   ((T(r_lo) + T(r_lo ^ x_lo)) - i (T(r_lo) - T(r_lo ^ x_lo))) / 2,
+// rebuilt per output row from the pair; the high transform over z_hi then runs in
+// registers and writes row (r_hi, r_lo), columns (r_hi ^ x_hi, r_lo ^ x_lo): the 8 lanes
+// of one r_lo write one 128-byte row segment.  The conjugate entry (row r ^ x) takes the
+// same sum and the negated difference and goes through the same butterflies with the
+// inputs weighted by a character, so mu is exactly Hermitian.  LDS: 2^H x 512 doubles.
+template <int H>
+struct RhoTileGeom {
+  static constexpr int NZ = 1 << H;
+  static constexpr int NV = NZ * 512;  // staged values
+};
+
+__device__ __forceinline__ int rho_tile_slot(uint32_t j, uint32_t w6) {
+  return (int)(((w6 >> 3) << 6) | letters_of<3>(j, w6 & 7u));
+}
+
+// Units [u0, u1) of one instance, in sequence; the next unit's inputs are loaded into
+// registers while the current one is transformed.  Every thread of the block calls this.
+template <int H, typename OutT, int THREADS>
+__device__ __forceinline__ void rho_tiles(const double* __restrict__ coef, void* __restrict__ rho, int64_t u0,
+                                          int64_t u1, int t, double* __restrict__ V) {
+  using G = RhoTileGeom<H>;
+  constexpr int n = 6 + H;
+  constexpr int PER = (G::NV + THREADS - 1) / THREADS;
+  static_assert(THREADS >= G::NZ * 32, "one lane quad per (z_hi, j) low transform");
+  double pre[PER];
+  auto load = [&](int64_t u) __attribute__((always_inline)) {
+    const uint32_t x_hi = (uint32_t)(u >> 3), xb = (uint32_t)(u & 7);
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = t + THREADS * i;
+      if (e < G::NV) {
+        const uint32_t z_hi = (uint32_t)e >> 9, zh3 = ((uint32_t)e >> 6) & 7u, l = (uint32_t)e & 63u;
+        const int64_t src = ((int64_t)letters_of<H>(x_hi, z_hi) << 12) | (letters_of<3>(xb, zh3) << 6) | l;
+        pre[i] = coef[src];
+      }
+    }
+  };
+  const double scale = ldexp(1.0, -n - 1);
+  if (u0 < u1) load(u0);
+  for (int64_t u = u0; u < u1; ++u) {
+    lds_barrier();  // the previous unit's high transform has read V
+#pragma unroll
+    for (int i = 0; i < PER; ++i)
+      if (t + THREADS * i < G::NV) V[t + THREADS * i] = pre[i];
+    lds_barrier();
+    if (u + 1 < u1) load(u + 1);
+    const uint32_t x_hi = (uint32_t)(u >> 3), xb = (uint32_t)(u & 7);
+    if (t < G::NZ * 32) {  // low transform: lane quad (z_hi, j), lane zl holds z_lo = zl + 4k
+      const uint32_t q = (uint32_t)t >> 2, zl = (uint32_t)t & 3u;
+      const uint32_t z_hi = q >> 3, j = q & 7u, x_lo = (xb << 3) | j;
+      double* __restrict__ Vz = V + z_hi * 512;
+      double v[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const uint32_t z = zl + 4u * (uint32_t)k;
+        const double a = Vz[rho_tile_slot(j, z)];
+        v[k] = (__popc(x_lo & z) & 2) ? -a : a;
+      }
+      wht_regs<4>(v);
+      int32_t sg[2] = {(t & 1) ? -1 : 1, (t & 2) ? -1 : 1};
+      asm volatile("" : "+v"(sg[0]), "+v"(sg[1]));
+#pragma unroll
+      for (int k = 0; k < 16; ++k) lane_bfly<kDppQuadXor1, false>(v[k], sg[0]);
+#pragma unroll
+      for (int k = 0; k < 16; ++k) lane_bfly<kDppQuadXor2, false>(v[k], sg[1]);
+#pragma unroll
+      for (int k = 0; k < 16; ++k) Vz[rho_tile_slot(j, zl + 4u * (uint32_t)k)] = v[k];
+    }
+    lds_barrier();
+    for (int w = t; w < 512; w += THREADS) {  // high transform: (r_lo, j), j fastest
+      const uint32_t r_lo = (uint32_t)w >> 3, j = (uint32_t)w & 7u;
+      const uint32_t rb = r_lo ^ ((xb << 3) | j);
+      const int sa = rho_tile_slot(j, r_lo), sb = rho_tile_slot(j, rb);
+      double re[G::NZ], im[G::NZ];
+#pragma unroll
+      for (int z = 0; z < G::NZ; ++z) {
+        const double ta = V[z * 512 + sa], tb = V[z * 512 + sb];
+        re[z] = ta + tb;
+        im[z] = tb - ta;
+        mul_neg_i_pow(__popc(x_hi & (uint32_t)z), re[z], im[z]);
+      }
+      wht_regs<H>(re);
+      wht_regs<H>(im);
+#pragma unroll
+      for (int r_hi = 0; r_hi < G::NZ; ++r_hi) {
+        const int64_t row = ((int64_t)r_hi << 6) | r_lo;
+        const int64_t col = ((int64_t)(r_hi ^ x_hi) << 6) | rb;
+        store_complex<OutT>(rho, (row << n) + col, re[r_hi] * scale, im[r_hi] * scale);
+      }
+    }
+  }
+}
+
+// Step (ii) for a single instance with n = 6 + H in [7, 10]: one unit per block.
+template <int H, typename OutT>
+__global__ __launch_bounds__(512) void rho_tile_kernel(const double* __restrict__ coef, void* __restrict__ rho) {
+  __shared__ double V[RhoTileGeom<H>::NV];
+  rho_tiles<H, OutT, 512>(coef, rho, blockIdx.x, (int64_t)blockIdx.x + 1, threadIdx.x, V);
 }
 
 // High transform for H = n - 6 in [5, 8] high qubits, 256 threads.  Block -> (x_hi, r_lo,
