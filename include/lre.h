@@ -194,8 +194,11 @@ typedef struct {
 /* Work-item shape of a plan (what lre_batch_tune chooses between). */
 typedef struct {
   int workers_per_cu;   /* persistent workgroups per compute unit: 1 or 2 */
-  int counts_tiles;     /* counts-pass row groups (3^7 rows, all their outcomes) per item, >= 1 */
-  int fold_cols;        /* later-pass columns per item, multiple of 432 */
+  int counts_tiles;     /* counts-pass row groups (3^7 rows, all their outcomes) per item at
+                           most, >= 1; an instance's groups are split into that many items
+                           of equal size (to one group) */
+  int fold_cols;        /* later-pass columns per item at most, multiple of 432 (split as
+                           evenly as counts_tiles) */
   int rho_blocks;       /* step-(ii) work per item, >= 1: high-qubit row patterns x_hi
                            (2^(n-6) per instance of n > 7 qubits) */
   int interleave;       /* 0: stage by stage, largest instances first;

@@ -463,8 +463,11 @@ bool valid_tiles(const lre_batch_tiles& t) {
 
 void add_range(std::vector<BItem>& out, int inst, Kind kind, uint8_t var, int64_t total, int64_t per,
                int32_t wait_ctr, uint32_t wait_target, int32_t done_ctr, uint32_t* count_out) {
+  // ceil(total / per) items of equal size (to one unit): an uneven last item would
+  // finish long after its siblings and hold up the stage that waits for all of them
+  const int64_t parts = (total + per - 1) / per;
   uint32_t c = 0;
-  for (int64_t b = 0; b < total; b += per) {
+  for (int64_t k = 0; k < parts; ++k) {
     BItem W{};
     W.inst = inst;
     W.kind = kind;
@@ -472,8 +475,8 @@ void add_range(std::vector<BItem>& out, int inst, Kind kind, uint8_t var, int64_
     W.wait_ctr = wait_ctr;
     W.wait_target = wait_target;
     W.done_ctr = done_ctr;
-    W.begin = b;
-    W.end = std::min(total, b + per);
+    W.begin = total * k / parts;
+    W.end = total * (k + 1) / parts;
     out.push_back(W);
     ++c;
   }
