@@ -81,7 +81,7 @@ def measured_traffic(workload):
     with open(path) as f:
         rec = json.load(f)
     from paper_1602_08604_amd.profsum import kernel_source_hash
-    if rec.get("kernel_source_hash") != kernel_source_hash():
+    if rec.get("kernel_source_hash") != kernel_source_hash(workload):
         return None
     return rec.get("hbm_bytes_per_launch")
 

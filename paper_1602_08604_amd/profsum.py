@@ -27,11 +27,14 @@ import statistics
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 KERNEL_SOURCES = ("paper_1602_08604_amd/csrc/lre_kernels.hpp", "paper_1602_08604_amd/csrc/lre_abi.hip")
+BATCH_SOURCES = KERNEL_SOURCES + ("paper_1602_08604_amd/csrc/lre_batch.hip",)
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(workload: str = "") -> str:
+    """Hash of the sources the workload's kernels are built from (the batch kernel also
+    lives in lre_batch.hip)."""
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in (BATCH_SOURCES if workload == "batch" else KERNEL_SOURCES):
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -104,7 +107,7 @@ def traffic(args):
     rec = {
         "kernel": kname,
         "workload": args.workload,
-        "kernel_source_hash": kernel_source_hash(),
+        "kernel_source_hash": kernel_source_hash(args.workload),
         "hbm_bytes_per_launch": read_b + write_b,
         "read_bytes_per_launch": read_b,
         "write_bytes_per_launch": write_b,
