@@ -65,7 +65,9 @@ typedef enum {
 /* Flags (bitwise or). */
 #define LRE_NO_RHO 0x1u    /* skip step (ii); rho may be NULL */
 #define LRE_RHO_FP32 0x2u  /* write rho as complex64 instead of complex128 */
-#define LRE_WHT_MFMA 0x4u  /* signed outcome sums on int8 MFMA (bit-identical results) */
+#define LRE_WHT_MFMA 0x4u  /* signed outcome sums on int8 MFMA: the same integer sums
+                              (bit-identical with uniform shots; per-basis binary64 sums
+                              added in another order, equal to rounding) */
 
 typedef struct lre_ctx lre_ctx;
 
