@@ -174,14 +174,19 @@ def test_ghz_exact(n, p_dep):
     assert np.max(np.abs(rho - refs.ghz_density(n, p_dep))) <= TOL
 
 
-def test_rho_fp32_error():
-    n = 8
-    counts = _haar_counts(n, 1000, 60)
-    coef, rho64 = L.estimate(_dev(counts), 1000)
-    _, rho32 = L.estimate(_dev(counts), 1000, flags=L.LRE_RHO_FP32)
-    err = (rho32.to(torch.complex128) - rho64).abs().max().item()
+@pytest.mark.parametrize("n", [5, 7, 8, 9, 10, 11, 12])
+def test_rho_fp32_is_rounded_fp64(n):
+    """LRE_RHO_FP32 writes the binary64 entries rounded to complex64: every step-(ii)
+    form (n <= 6 in LDS, the tiles for 7 <= n <= 10, the intermediate for n >= 11) gives
+    exactly the complex128 result converted."""
+    import tomo_inputs.gpu as tg
+    print(f"[rho fp32 n={n}]", flush=True)
+    counts, nb = tg.philox_counts(n, 0x1602_0860_4F + n, device=DEV)
+    coef, rho64 = L.estimate(counts, 0, n_per_basis=nb)
+    _, rho32 = L.estimate(counts, 0, n_per_basis=nb, flags=L.LRE_RHO_FP32)
     assert rho32.dtype == torch.complex64
-    assert err < 1e-7
+    assert torch.equal(rho32, rho64.to(torch.complex64))
+    assert (rho32.to(torch.complex128) - rho64).abs().max().item() < 1e-7
 
 
 def test_no_rho_flag():
