@@ -138,7 +138,7 @@ __device__ __forceinline__ void small_rho(const BInstG& I, int tid, double* re, 
 }
 
 template <int Q, bool MAD24, bool PREFETCH>
-__device__ __noinline__ void run_small(const BInstG& I, uint8_t var, int tid, LRE_GLOBAL char* ws, LRE_LDS char* smem,
+__device__ __noinline__ void run_small(const BInstG& I, uint8_t var, int tid, LRE_LDS char* smem,
                                        uint32_t* flags) {
   uint32_t* acc = l2p<uint32_t>(smem);
   uint32_t* rs = acc + StreamGeom<Q>::NACC;
@@ -298,18 +298,18 @@ __device__ __noinline__ void run_rho(const BInstG& I, int64_t x0, int64_t x1, in
 }
 
 template <bool PREFETCH>
-__device__ __forceinline__ void dispatch_small(const BInstG& I, uint8_t var, int tid, LRE_GLOBAL char* ws, LRE_LDS char* smem,
+__device__ __forceinline__ void dispatch_small(const BInstG& I, uint8_t var, int tid, LRE_LDS char* smem,
                                                uint32_t* flags) {
   switch (I.n) {
-    case 1: run_small<1, false, PREFETCH>(I, var, tid, ws, smem, flags); break;
-    case 2: run_small<2, false, PREFETCH>(I, var, tid, ws, smem, flags); break;
-    case 3: run_small<3, false, PREFETCH>(I, var, tid, ws, smem, flags); break;
-    case 4: run_small<4, false, PREFETCH>(I, var, tid, ws, smem, flags); break;
-    case 5: run_small<5, false, PREFETCH>(I, var, tid, ws, smem, flags); break;
-    case 6: run_small<6, false, PREFETCH>(I, var, tid, ws, smem, flags); break;
+    case 1: run_small<1, false, PREFETCH>(I, var, tid, smem, flags); break;
+    case 2: run_small<2, false, PREFETCH>(I, var, tid, smem, flags); break;
+    case 3: run_small<3, false, PREFETCH>(I, var, tid, smem, flags); break;
+    case 4: run_small<4, false, PREFETCH>(I, var, tid, smem, flags); break;
+    case 5: run_small<5, false, PREFETCH>(I, var, tid, smem, flags); break;
+    case 6: run_small<6, false, PREFETCH>(I, var, tid, smem, flags); break;
     default:
-      if (var & V_MAD24) run_small<7, true, PREFETCH>(I, var, tid, ws, smem, flags);
-      else run_small<7, false, PREFETCH>(I, var, tid, ws, smem, flags);
+      if (var & V_MAD24) run_small<7, true, PREFETCH>(I, var, tid, smem, flags);
+      else run_small<7, false, PREFETCH>(I, var, tid, smem, flags);
       break;
   }
 }
@@ -384,7 +384,7 @@ __global__ __launch_bounds__(kBT, WORKERS == 2 ? 4 : 1) void batch_kernel(
             break;
           }
         }
-        dispatch_small<PF>(I, W.variant, tid, ws, smem, flags);
+        dispatch_small<PF>(I, W.variant, tid, smem, flags);
         break;
       case K_COUNTS:
         if constexpr (PB) {

@@ -178,12 +178,16 @@ def test_ghz_exact(n, p_dep):
 def test_rho_fp32_is_rounded_fp64(n):
     """LRE_RHO_FP32 writes the binary64 entries rounded to complex64: every step-(ii)
     form (n <= 6 in LDS, the tiles for 7 <= n <= 10, the intermediate for n >= 11) gives
-    exactly the complex128 result converted."""
+    exactly the complex128 result converted.  Uniform shots (paired Philox counts), so
+    that the two calls' coefficients are the same exact integer quotients (per-basis
+    binary64 sums can differ in the last bit between calls: LDS atomics from different
+    waves land in run-dependent order)."""
     import tomo_inputs.gpu as tg
     print(f"[rho fp32 n={n}]", flush=True)
-    counts, nb = tg.philox_counts(n, 0x1602_0860_4F + n, device=DEV)
-    coef, rho64 = L.estimate(counts, 0, n_per_basis=nb)
-    _, rho32 = L.estimate(counts, 0, n_per_basis=nb, flags=L.LRE_RHO_FP32)
+    counts, _ = tg.philox_counts(n, 0x1602_0860_4F + n, device=DEV, paired=True)
+    shots = 12 << (n - 1)
+    coef, rho64 = L.estimate(counts, shots)
+    _, rho32 = L.estimate(counts, shots, flags=L.LRE_RHO_FP32)
     assert rho32.dtype == torch.complex64
     assert torch.equal(rho32, rho64.to(torch.complex64))
     assert (rho32.to(torch.complex128) - rho64).abs().max().item() < 1e-7
