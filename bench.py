@@ -196,7 +196,7 @@ def measured_hbm(torch, lre, gib=8, reps=5):
     del x, y, sink
     torch.cuda.empty_cache()
     return {"stream_read_gbs": read, "stream_copy_gbs": copy, "unit": "GB/s", "bytes_each": nbytes,
-            "how": f"lre_stream_read / lre_stream_copy (16-byte vectors, a contiguous range per block) over {gib} GiB, "
+            "how": f"lre_stream_read / lre_stream_copy (16-byte nontemporal vectors, a contiguous range per block) over {gib} GiB, "
                    f"{reps} reps each; copy counts read + write bytes"}
 
 
