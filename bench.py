@@ -200,6 +200,32 @@ def measured_hbm(torch, lre, gib=8, reps=5):
                    f"{reps} reps each; copy counts read + write bytes"}
 
 
+def measured_compute(torch, lre, reps=5):
+    """Issue rates of the two compute paths next to their datasheet peaks: 32-bit
+    integer adds (lre_peak_valu_i32) and dense int8 MFMA (lre_peak_mfma_i8), each timed
+    with events over `reps` launches after one warm-up."""
+    sink = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+
+    def rate(kind, iters):
+        lre.peak_rate(kind, iters, sink)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ops = 0.0
+        for _ in range(reps):
+            ops += lre.peak_rate(kind, iters, sink)
+        e1.record()
+        torch.cuda.synchronize()
+        return ops / (e0.elapsed_time(e1) / 1e3) / 1e12
+
+    valu = rate("valu_i32", 2000)
+    mfma = rate("mfma_i8", 20000)
+    return {"valu_int32_tops": valu, "valu_int32_datasheet_tops": 78.6, "mfma_int8_tops": mfma,
+            "mfma_int8_datasheet_tops": 5000.0, "unit": "Tops",
+            "how": "lre_peak_valu_i32 (8 independent add chains per lane) and lre_peak_mfma_i8 "
+                   "(4 independent v_mfma_i32_16x16x64_i8 chains per wave), 8 workgroups of 256 per CU, "
+                   f"{reps} launches each"}
+
+
 def host_cpu():
     """Model name and logical CPU count of the host the oracle runs on."""
     model = "unknown"
@@ -596,6 +622,7 @@ def bench_batch(args, torch, lre):
                                          f"({t_full:.0f} s)"}
     b.close()
     out["hbm_measured"] = measured_hbm(torch, lre)
+    out["compute_measured"] = measured_compute(torch, lre)
     print(json.dumps(out), flush=True)
 
 
@@ -764,6 +791,7 @@ def bench_estimate(workload, args, torch, lre, extras):
         del counts, ws, rho, coef, nb
         torch.cuda.empty_cache()
         out["hbm_measured"] = measured_hbm(torch, lre)
+        out["compute_measured"] = measured_compute(torch, lre)
     return out
 
 

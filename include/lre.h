@@ -372,6 +372,17 @@ lre_status lre_project(lre_ctx* ctx, int n, const void* mu, void* rho, double* e
 lre_status lre_stream_read(const void* buf, size_t bytes, uint32_t* sink, void* stream);
 lre_status lre_stream_copy(const void* src, void* dst, size_t bytes, void* stream);
 
+/* Compute issue rates (diagnostics, not part of the method), next to the datasheet
+ * peaks the counts pass is judged against.  Each launches one kernel of `iters`
+ * iterations on `stream` (time it with events around the call) and stores in *ops
+ * (host pointer, may be NULL) the number of operations the launch performs:
+ *   lre_peak_valu_i32 : 32-bit integer adds, 8 independent chains per lane;
+ *   lre_peak_mfma_i8  : dense int8 MFMA (v_mfma_i32_16x16x64_i8, 32768 operations each),
+ *                       4 independent accumulator chains per wave.
+ * `sink` is a device uint32 that may be written.  iters < 1 or sink NULL: LRE_E_ARG. */
+lre_status lre_peak_valu_i32(int iters, uint32_t* sink, double* ops, void* stream);
+lre_status lre_peak_mfma_i8(int iters, uint32_t* sink, double* ops, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

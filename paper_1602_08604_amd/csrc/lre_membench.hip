@@ -56,6 +56,50 @@ __global__ __launch_bounds__(kThreads) void stream_copy_kernel(const lre_u32x4* 
   for (; i < b1; i += kThreads) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
+// Peak issue rates of the two compute paths the counts pass can take (diagnostics).
+// int32 adds: 8 independent chains per lane, 16 rounds per iteration.
+constexpr int kPeakBlocksPerCu = 8;
+constexpr int kValuChains = 8, kValuRounds = 16;
+
+__global__ __launch_bounds__(kThreads) void peak_valu_kernel(int iters, uint32_t* __restrict__ sink) {
+  uint32_t a[kValuChains];
+#pragma unroll
+  for (int c = 0; c < kValuChains; ++c) a[c] = threadIdx.x * 2654435761u + (uint32_t)c;
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int r = 0; r < kValuRounds; ++r) {
+#pragma unroll
+      for (int c = 0; c < kValuChains; ++c) a[c] += a[(c + 1) % kValuChains];
+    }
+  }
+  uint32_t v = 0;
+#pragma unroll
+  for (int c = 0; c < kValuChains; ++c) v ^= a[c];
+  if (v == 0x9E3779B9u) sink[0] = v;
+}
+
+// int8 MFMA: 4 independent accumulator chains per wave of v_mfma_i32_16x16x64_i8
+// (2 * 16 * 16 * 64 operations each).
+typedef int lre_i32x4 __attribute__((ext_vector_type(4)));
+constexpr int kMfmaChains = 4;
+
+__global__ __launch_bounds__(kThreads) void peak_mfma_kernel(int iters, uint32_t* __restrict__ sink) {
+  const int t = (int)threadIdx.x;
+  const lre_i32x4 a = {t, t + 1, t + 2, t + 3};
+  const lre_i32x4 b = {3 * t, t ^ 5, t + 7, 11};
+  lre_i32x4 c[kMfmaChains];
+#pragma unroll
+  for (int k = 0; k < kMfmaChains; ++k) c[k] = lre_i32x4{k, 0, 0, 0};
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int k = 0; k < kMfmaChains; ++k) c[k] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, c[k], 0, 0, 0);
+  }
+  int v = 0;
+#pragma unroll
+  for (int k = 0; k < kMfmaChains; ++k) v ^= c[k].x ^ c[k].y ^ c[k].z ^ c[k].w;
+  if (v == 0x1234567) sink[0] = (uint32_t)v;
+}
+
 unsigned stream_blocks(int per_cu) {
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
@@ -75,6 +119,22 @@ lre_status lre_stream_read(const void* buf, size_t bytes, uint32_t* sink, void* 
   if (bytes == 0) return LRE_OK;
   hipLaunchKernelGGL(stream_read_kernel, dim3(stream_blocks(kReadBlocksPerCu)), dim3(kThreads), 0, (hipStream_t)stream,
                      static_cast<const lre_u32x4*>(buf), (int64_t)(bytes / 16), sink);
+  return hipGetLastError() == hipSuccess ? LRE_OK : LRE_E_HIP;
+}
+
+lre_status lre_peak_valu_i32(int iters, uint32_t* sink, double* ops, void* stream) {
+  if (iters < 1 || !sink) return LRE_E_ARG;
+  const unsigned grid = stream_blocks(kPeakBlocksPerCu);
+  if (ops) *ops = (double)grid * kThreads * (double)iters * kValuRounds * kValuChains;
+  hipLaunchKernelGGL(peak_valu_kernel, dim3(grid), dim3(kThreads), 0, (hipStream_t)stream, iters, sink);
+  return hipGetLastError() == hipSuccess ? LRE_OK : LRE_E_HIP;
+}
+
+lre_status lre_peak_mfma_i8(int iters, uint32_t* sink, double* ops, void* stream) {
+  if (iters < 1 || !sink) return LRE_E_ARG;
+  const unsigned grid = stream_blocks(kPeakBlocksPerCu);
+  if (ops) *ops = (double)grid * (kThreads / 64) * (double)iters * kMfmaChains * (2.0 * 16 * 16 * 64);
+  hipLaunchKernelGGL(peak_mfma_kernel, dim3(grid), dim3(kThreads), 0, (hipStream_t)stream, iters, sink);
   return hipGetLastError() == hipSuccess ? LRE_OK : LRE_E_HIP;
 }
 

@@ -107,6 +107,9 @@ def lib():
         L.lre_stream_read.restype = I
         L.lre_stream_copy.argtypes = [P, P, SZ, P]
         L.lre_stream_copy.restype = I
+        for name in ("lre_peak_valu_i32", "lre_peak_mfma_i8"):
+            getattr(L, name).argtypes = [I, P, ctypes.POINTER(ctypes.c_double), P]
+            getattr(L, name).restype = I
         L.lre_batch_destroy.argtypes = [P]
         L.lre_batch_destroy.restype = None
         L.lre_stream_create.argtypes = [P, I, I, U64, U32, ctypes.POINTER(P)]
@@ -366,6 +369,18 @@ def stream_copy(src: torch.Tensor, dst: torch.Tensor) -> None:
         raise ValueError("src, dst: contiguous device tensors of equal size")
     _ok(lib().lre_stream_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), nbytes,
                               ctypes.c_void_p(_stream(src.device))), "lre_stream_copy")
+
+
+def peak_rate(kind: str, iters: int, sink: torch.Tensor) -> float:
+    """lre_peak_valu_i32 (kind "valu_i32") or lre_peak_mfma_i8 (kind "mfma_i8"): enqueue
+    one launch on sink's device and return the number of operations it performs."""
+    if not (sink.is_cuda and sink.dtype == torch.int32):
+        raise ValueError("sink: int32 device tensor")
+    fn = {"valu_i32": lib().lre_peak_valu_i32, "mfma_i8": lib().lre_peak_mfma_i8}[kind]
+    ops = ctypes.c_double(0.0)
+    _ok(fn(int(iters), ctypes.c_void_p(sink.data_ptr()), ctypes.byref(ops), ctypes.c_void_p(_stream(sink.device))),
+        f"lre_peak_{kind}")
+    return ops.value
 
 
 def set_stage_events(events, device=None):

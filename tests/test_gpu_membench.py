@@ -23,3 +23,17 @@ def test_stream_copy_and_read(n):
     torch.cuda.synchronize()
     assert torch.equal(src, dst)
     assert int(sink.item()) in (0, 0x9E3779B9 - 2 ** 32)
+
+
+@pytest.mark.parametrize("kind", ["valu_i32", "mfma_i8"])
+def test_peak_rate_diagnostics(kind):
+    """The compute-rate diagnostics run, report their operation count and leave the sink
+    alone; bad arguments are refused."""
+    print(f"[peak {kind}]", flush=True)
+    sink = torch.zeros(1, dtype=torch.int32, device=DEV)
+    ops = L.peak_rate(kind, 3, sink)
+    torch.cuda.synchronize()
+    assert ops > 0 and int(sink.item()) == 0
+    with pytest.raises(L.LreError) as e:
+        L.peak_rate(kind, 0, sink)
+    assert e.value.status == L.LRE_E_ARG
