@@ -736,6 +736,32 @@ def bench_estimate(workload, args, torch, lre, extras):
         del src, dst
     ms_step = head["ms_step"]
     pass1, step_i, step_ii = head["pass1"], head["step_i"], head["step_ii"]
+    graph = None
+    if n <= 10:
+        # launch-bound sizes: the same step captured into a HIP graph and replayed
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            lre.estimate(counts, shots, n_per_basis=nb, coef=coef, rho=rho, workspace=ws, flags=head_flags,
+                         check=False)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            lre.estimate(counts, shots, n_per_basis=nb, coef=coef, rho=rho, workspace=ws, flags=head_flags,
+                         check=False)
+        for _ in range(args.warmup):
+            g.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            g.replay()
+        torch.cuda.synchronize()
+        graph = {"ms_per_step": (time.perf_counter() - t0) * 1e3 / args.steps,
+                 "how": "one lre_estimate captured into a HIP graph (torch.cuda.CUDAGraph), replayed per step"}
+        lre.check_flags("cuda:0")
+        print(f"[bench] {workload}: graph replay {graph['ms_per_step']:.4f} ms/step", file=sys.stderr, flush=True)
+        del g
 
     n_counts = 3 ** n * d
     t_pass1 = sum(pass1) / len(pass1) / 1e3
@@ -768,6 +794,8 @@ def bench_estimate(workload, args, torch, lre, extras):
         "wht": "int8-mfma" if head_flags else "plain-int32",
         "mfma_vs_plain": None,
     }
+    if graph is not None:
+        out["graph_replay"] = graph
     if other is not None:
         mfma, plain = (head, other) if head_flags else (other, head)
         mean = lambda v: sum(v) / len(v)

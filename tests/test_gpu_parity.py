@@ -193,6 +193,56 @@ def test_rho_fp32_is_rounded_fp64(n):
     assert (rho32.to(torch.complex128) - rho64).abs().max().item() < 1e-7
 
 
+@pytest.mark.parametrize("n,flags", [(4, 0), (8, 0), (8, "mfma"), (10, 0), (12, "mfma")])
+def test_estimate_graph_replay(n, flags):
+    """lre_estimate enqueues kernels only, so a caller can capture one step into a HIP
+    graph: every replay (outputs cleared before it, eager estimates of other counts and
+    synchronisations between replays) equals the eager call bit for bit, and a data error
+    raised inside a replay still reaches the flag word."""
+    import tomo_inputs.gpu as tg
+    print(f"[graph replay n={n} flags={flags}]", flush=True)
+    fl = L.LRE_WHT_MFMA if flags == "mfma" else 0
+    counts, _ = tg.philox_counts(n, 0x6A0 + n, device=DEV, paired=True)
+    other, _ = tg.philox_counts(n, 0x6B0 + n, device=DEV, paired=True)
+    shots = 12 << (n - 1)
+    ref_coef, ref_rho = L.estimate(counts, shots, flags=fl)
+    coef = torch.empty_like(ref_coef)
+    rho = torch.empty_like(ref_rho)
+    ws = torch.empty(max(L.workspace_bytes(n, shots, fl), 1), dtype=torch.uint8, device=DEV)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        L.estimate(counts, shots, flags=fl, coef=coef, rho=rho, workspace=ws, check=False)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        L.estimate(counts, shots, flags=fl, coef=coef, rho=rho, workspace=ws, check=False)
+    for k in range(3):
+        coef.zero_()
+        rho.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        L.check_flags(DEV)
+        assert torch.equal(coef, ref_coef), f"replay {k}: coefficients"
+        assert torch.equal(rho, ref_rho), f"replay {k}: rho"
+        oc, orho = L.estimate(other, shots, flags=fl)      # eager work between replays
+        assert not torch.equal(oc, ref_coef)
+        del oc, orho
+    del g
+    # a capture whose shot count disagrees with the rows: the replay sets the flag
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        L.estimate(counts, shots + 1, flags=fl, coef=coef, rho=rho, workspace=ws, check=False)
+    g.replay()
+    with pytest.raises(L.LreError) as e:
+        L.check_flags(DEV)
+    assert e.value.status == L.LRE_E_SHOTS
+    del g
+    coef2, _ = L.estimate(counts, shots, flags=fl)
+    assert torch.equal(coef2, ref_coef)
+
+
 def test_no_rho_flag():
     counts = _haar_counts(6, 100, 61)
     coef, rho = L.estimate(_dev(counts), 100, flags=L.LRE_NO_RHO)
