@@ -34,6 +34,9 @@ constexpr int kMaxFLast = 2;  // qubits folded by the final pass (below kMinHF4)
 constexpr int kMinHF4 = 5;    // from this many unfolded qubits on, the first later pass
                               // folds 4 with LDS accumulators and the final one the rest
 constexpr int kRhoJ = 6;      // qubits of the low step-(ii) transform
+// Step (ii) goes through a complex128 intermediate of 4^n entries only beyond 12 qubits
+// (up to 10 the LDS tiles, at 11 and 12 the real-arithmetic tiles need none).
+constexpr bool rho_needs_tmp(int n) { return n > kRhoJ + 6; }
 
 enum class Ty : int { U32 = 0, F64 = 1 };
 
@@ -120,7 +123,7 @@ bool make_plan(int n, uint64_t shots, uint32_t flags, Plan& P) {
   const size_t rowpart = (size_t)P.blocks1 * (size_t)ipow3(P.q1) * 4;
   const size_t nbytes = P.per_basis ? (size_t)ipow3(n) * 4 : 0;
   P.J = n < kRhoJ ? n : kRhoJ;
-  const size_t tmp = (!(flags & LRE_NO_RHO) && n > P.J) ? (size_t)ipow4(n) * 16 : 0;
+  const size_t tmp = (!(flags & LRE_NO_RHO) && rho_needs_tmp(n)) ? (size_t)ipow4(n) * 16 : 0;
 
   size_t off = 0;
   P.off_a = off; off += align256(sizeA);
@@ -362,6 +365,14 @@ void launch_rho_high2(const double2* tmp, void* rho, int n, hipStream_t st) {
   hipLaunchKernelGGL((rho_high2_kernel<H, OutT>), dim3((unsigned)blocks), dim3(256), 0, st, tmp, rho, n, items);
 }
 
+template <int H, int JB, typename OutT>
+void launch_rho_real(const double* coef, void* rho, hipStream_t st) {
+  using G = RhoRealGeom<H, JB>;
+  const int64_t blocks = std::min<int64_t>(
+      G::UNITS, resident_blocks(rho_real_tile_kernel<H, JB, OutT>, 512, (int64_t)G::NVP * 8));
+  hipLaunchKernelGGL((rho_real_tile_kernel<H, JB, OutT>), dim3((unsigned)blocks), dim3(512), 0, st, coef, rho);
+}
+
 template <typename OutT>
 void launch_rho(const Plan& P, const double* coef, void* rho, char* ws, hipStream_t st) {
   const int n = P.n;
@@ -383,6 +394,12 @@ void launch_rho(const Plan& P, const double* coef, void* rho, char* ws, hipStrea
       case 3: hipLaunchKernelGGL((rho_tile_kernel<3, OutT>), grid, dim3(512), 0, st, coef, rho); break;
       default: hipLaunchKernelGGL((rho_tile_kernel<4, OutT>), grid, dim3(512), 0, st, coef, rho); break;
     }
+    return;
+  }
+  if (n - kRhoJ <= 6) {
+    // 5 or 6 high qubits: real-arithmetic units (x_hi, 8 or 4 x_lo), no intermediate
+    if (n - kRhoJ == 5) launch_rho_real<5, 3, OutT>(coef, rho, st);
+    else launch_rho_real<6, 2, OutT>(coef, rho, st);
     return;
   }
   double2* tmp = reinterpret_cast<double2*>(ws + P.off_tmp);
@@ -908,7 +925,7 @@ void lre_stream_destroy(lre_stream* S) {
 size_t lre_povm_workspace_bytes(int n, uint32_t flags) {
   if (n < 1 || n > LRE_MAX_QUBITS) return 0;
   const size_t head = 256;   // M (16 binary64) and the 64-bit total N
-  const size_t tmp = (!(flags & LRE_NO_RHO) && n > kRhoJ) ? (size_t)ipow4(n) * 16 : 0;
+  const size_t tmp = (!(flags & LRE_NO_RHO) && rho_needs_tmp(n)) ? (size_t)ipow4(n) * 16 : 0;
   return head + align256(tmp);
 }
 

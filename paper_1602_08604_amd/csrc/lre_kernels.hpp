@@ -33,7 +33,10 @@
 // the Omega_i by nonzero pattern, Sec. IV).  n <= 6: rho_low_kernel does all of it in
 // LDS.  7 <= n <= 10: rho_tile_kernel, units of one high pattern and 8 low patterns
 // from coefficients to mu in LDS (a real low transform, the complex one rebuilt from
-// pairs of its outputs, the high transform in registers).  n > 10: rho_low6_kernel
+// pairs of its outputs, the high transform in registers).  n = 11, 12:
+// rho_real_tile_kernel, the whole n-qubit transform real (the sign (-1)^{floor(|x&z|/2)}
+// applied on input) and the complex entry rebuilt from the outputs at r and r^x, units
+// of one high pattern and 8 or 4 low patterns in LDS.  n > 12: rho_low6_kernel
 // transforms the low 6 qubits of each 4^6 coefficient block (registers + lane quads)
 // into a complex intermediate, then rho_high2_kernel (5 to 9 high qubits, two register
 // phases and one LDS transpose) the remaining high qubits, writing the row-major
@@ -1438,6 +1441,16 @@ __device__ __forceinline__ void store_complex(void* base, int64_t idx, double re
   }
 }
 
+// store_complex with the nontemporal hint (mu is not read again by the library; its
+// lines then reach HBM during the kernel instead of being written back from the caches
+// during whatever runs next).
+template <typename OutT>
+__device__ __forceinline__ void store_complex_nt(void* base, int64_t idx, double re, double im) {
+  OutT* p = reinterpret_cast<OutT*>(base) + 2 * idx;
+  __builtin_nontemporal_store((OutT)re, p);
+  __builtin_nontemporal_store((OutT)im, p + 1);
+}
+
 // Transform the low J qubits of one 4^J block of coefficients (block = high letters).
 // FINAL (J == n): writes mu directly.  Otherwise tmp[a_hi][r_lo][x_lo] (complex128).
 template <int J>
@@ -1720,6 +1733,144 @@ template <int H, typename OutT>
 __global__ __launch_bounds__(512) void rho_tile_kernel(const double* __restrict__ coef, void* __restrict__ rho) {
   __shared__ double V[RhoTileGeom<H>::NV];
   rho_tiles<H, OutT, 512>(coef, rho, blockIdx.x, (int64_t)blockIdx.x + 1, threadIdx.x, V);
+}
+
+// Step (ii) for n = 6 + H with no intermediate in device memory, in real arithmetic up
+// to the last step (n = 11, 12).  For a fixed pattern x the values
+//   g(z) = e_{a(x,z)} (-1)^{floor(|x & z| / 2)}
+// are real; with G their n-bit Walsh-Hadamard transform, (-i)^k = (-1)^{floor(k/2)}
+// (-i)^{k mod 2} and k mod 2 = x . z (a character of z) give
+//   2^n mu[r][r ^ x] = ((G(r) + G(r ^ x)) - i (G(r) - G(r ^ x))) / 2.
+// A unit is a high pattern x_hi and XB = 2^JB consecutive low patterns x_lo = XB xb + j
+// (unit index (x_hi << (6 - JB)) | xb).  Its inputs, 2^H x 64 x XB coefficients, are
+// staged in LDS as V[z_hi][z_lo >> JB][letters of qubits 0..JB-1] (runs of 4^JB
+// consecutive coefficients, each z_hi row padded by 16 doubles).  The low transform runs
+// per (z_hi, j) in a lane quad (registers and DPP), the high one per slot in two phases
+// of at most 3 bits, all in place; every output row then takes one segment of XB
+// entries.  Coefficients are read and mu written with the nontemporal hint.  The
+// entry at (r ^ x, r) is built from the same two values with the difference negated, so
+// mu is exactly Hermitian.
+template <int H, int JB>
+struct RhoRealGeom {
+  static constexpr int XB = 1 << JB, NZ = 1 << H, PZ = 64 * XB, PZP = PZ + 16;
+  static constexpr int NV = NZ * PZ, NVP = NZ * PZP;   // values; LDS doubles
+  static constexpr int64_t UNITS = (int64_t)NZ << (6 - JB);
+};
+
+template <int JB>
+__device__ __forceinline__ int rho_real_slot(uint32_t j, uint32_t z_lo) {
+  return (int)(((z_lo >> JB) << (2 * JB)) | letters_of<JB>(j, z_lo & ((1u << JB) - 1u)));
+}
+
+// Work index -> unit: indices i and i + 8 (consecutive workgroups on one XCD, since
+// workgroups go round-robin over the 8 XCDs) get the units of x_lo blocks 2m and 2m + 1,
+// which write the two halves of the same rows' 128-byte segments.  A bijection of
+// [0, 2^k) for k >= 4.
+__device__ __forceinline__ int64_t rho_pair_unit(int64_t i) {
+  return ((((i >> 4) << 3) | (i & 7)) << 1) | ((i >> 3) & 1);
+}
+
+// Walsh-Hadamard transform over bits [B0, B0 + B) of the row index z of V[z][slot],
+// in place, for all PZ slots (rows PZP doubles apart).
+template <int H, int B0, int B, int PZ, int PZP, int THREADS>
+__device__ __forceinline__ void rho_real_high(double* __restrict__ V, int t) {
+  constexpr int NG = (1 << H) >> B;   // values of the other H - B bits
+  for (int w = t; w < PZ * NG; w += THREADS) {
+    const int s = w % PZ, grp = w / PZ;
+    const int base = (grp & ((1 << B0) - 1)) | ((grp >> B0) << (B0 + B));
+    double g[1 << B];
+#pragma unroll
+    for (int k = 0; k < (1 << B); ++k) g[k] = V[(base | (k << B0)) * PZP + s];
+    wht_regs<B>(g);
+#pragma unroll
+    for (int k = 0; k < (1 << B); ++k) V[(base | (k << B0)) * PZP + s] = g[k];
+  }
+}
+
+// Work indices i0, i0 + istride, ... < UNITS in sequence; the next unit's inputs are
+// loaded into registers while the current one is transformed.
+template <int H, int JB, typename OutT, int THREADS>
+__device__ __forceinline__ void rho_real_units(const double* __restrict__ coef, void* __restrict__ rho, int64_t i0,
+                                               int64_t istride, int t, double* __restrict__ V) {
+  using G = RhoRealGeom<H, JB>;
+  constexpr int n = 6 + H, XB = G::XB, PZ = G::PZ, PZP = G::PZP;
+  constexpr uint32_t JM = XB - 1;
+  constexpr int PER = (G::NV + THREADS - 1) / THREADS;
+  static_assert(THREADS % 4 == 0, "whole lane quads");
+  double pre[PER];
+  auto load = [&](int64_t u) __attribute__((always_inline)) {
+    const uint32_t x_hi = (uint32_t)(u >> (6 - JB)), xb = (uint32_t)u & ((1u << (6 - JB)) - 1u);
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = t + THREADS * i;
+      if (e < G::NV) {
+        const uint32_t z_hi = (uint32_t)e / PZ, w = (uint32_t)e % PZ;
+        const uint32_t zh = w >> (2 * JB), l = w & ((1u << (2 * JB)) - 1u);
+        pre[i] = __builtin_nontemporal_load(
+            &coef[((int64_t)letters_of<H>(x_hi, z_hi) << 12) | (letters_of<6 - JB>(xb, zh) << (2 * JB)) | l]);
+      }
+    }
+  };
+  const double scale = ldexp(1.0, -n - 1);
+  if (i0 < G::UNITS) load(rho_pair_unit(i0));
+  for (int64_t i = i0; i < G::UNITS; i += istride) {
+    const int64_t u = rho_pair_unit(i);
+    lds_barrier();  // the previous unit's output has read V
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int e = t + THREADS * k;
+      if (e < G::NV) V[(e / PZ) * PZP + e % PZ] = pre[k];
+    }
+    lds_barrier();
+    if (i + istride < G::UNITS) load(rho_pair_unit(i + istride));
+    const uint32_t x_hi = (uint32_t)(u >> (6 - JB)), xb = (uint32_t)u & ((1u << (6 - JB)) - 1u);
+    // low transform: lane quad (z_hi, j), lane zl holds z_lo = zl + 4k
+    for (int q4 = t; q4 < G::NZ * XB * 4; q4 += THREADS) {
+      const uint32_t q = (uint32_t)q4 >> 2, zl = (uint32_t)q4 & 3u;
+      const uint32_t z_hi = q >> JB, j = q & JM, x_lo = (xb << JB) | j;
+      const uint32_t hs = __popc(x_hi & z_hi);
+      double* __restrict__ Vz = V + z_hi * PZP;
+      double v[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const uint32_t z = zl + 4u * (uint32_t)k;
+        const double a = Vz[rho_real_slot<JB>(j, z)];
+        v[k] = ((__popc(x_lo & z) + hs) & 2) ? -a : a;
+      }
+      wht_regs<4>(v);
+      int32_t sg[2] = {(q4 & 1) ? -1 : 1, (q4 & 2) ? -1 : 1};
+      asm volatile("" : "+v"(sg[0]), "+v"(sg[1]));
+#pragma unroll
+      for (int k = 0; k < 16; ++k) lane_bfly<kDppQuadXor1, false>(v[k], sg[0]);
+#pragma unroll
+      for (int k = 0; k < 16; ++k) lane_bfly<kDppQuadXor2, false>(v[k], sg[1]);
+#pragma unroll
+      for (int k = 0; k < 16; ++k) Vz[rho_real_slot<JB>(j, zl + 4u * (uint32_t)k)] = v[k];
+    }
+    lds_barrier();
+    // high transform: the 2^H values of every slot, z_hi bits 0-2, then the rest
+    rho_real_high<H, 0, (H < 3 ? H : 3), PZ, PZP, THREADS>(V, t);
+    if constexpr (H > 3) {
+      lds_barrier();
+      rho_real_high<H, 3, H - 3, PZ, PZP, THREADS>(V, t);
+    }
+    lds_barrier();
+    // output: (r_hi, r_lo, j), j fastest: XB lanes write one row segment
+    for (int e = t; e < G::NZ * 64 * XB; e += THREADS) {
+      const uint32_t j = (uint32_t)e & JM, r_lo = ((uint32_t)e >> JB) & 63u, r_hi = (uint32_t)e >> (JB + 6);
+      const uint32_t rb = r_lo ^ ((xb << JB) | j), rh = r_hi ^ x_hi;
+      const double ta = V[r_hi * PZP + rho_real_slot<JB>(j, r_lo)];
+      const double tb = V[rh * PZP + rho_real_slot<JB>(j, rb)];
+      const int64_t row = ((int64_t)r_hi << 6) | r_lo, col = ((int64_t)rh << 6) | rb;
+      store_complex_nt<OutT>(rho, (row << n) + col, (ta + tb) * scale, (tb - ta) * scale);
+    }
+  }
+}
+
+template <int H, int JB, typename OutT>
+__global__ __launch_bounds__(512) void rho_real_tile_kernel(const double* __restrict__ coef, void* __restrict__ rho) {
+  __shared__ double V[RhoRealGeom<H, JB>::NVP];
+  rho_real_units<H, JB, OutT, 512>(coef, rho, blockIdx.x, gridDim.x, threadIdx.x, V);
 }
 
 // High transform for H = n - 6 in [5, 8] high qubits, 256 threads.  Block -> (x_hi, r_lo,

@@ -243,6 +243,29 @@ def test_estimate_graph_replay(n, flags):
     assert torch.equal(coef2, ref_coef)
 
 
+@pytest.mark.parametrize("n", [11, 12])
+def test_rho_real_tiles_full_rows(n):
+    """Step (ii) at 11 and 12 qubits (real-arithmetic tiles, no intermediate): whole rows
+    of rho -- every column pattern x, so every tile -- against eq. (4) on the GPU's
+    coefficients, rho exactly Hermitian with unit trace, for complex128 and complex64."""
+    import tomo_inputs.gpu as tg
+    print(f"[rho real tiles n={n}]", flush=True)
+    counts, _ = tg.philox_counts(n, 0x7A11 + n, device=DEV, paired=True)
+    shots = 12 << (n - 1)
+    coef, rho = L.estimate(counts, shots)
+    e = coef.cpu().numpy()
+    d = 2 ** n
+    rows = np.array([0, d - 1] + list(np.random.default_rng(n).integers(0, d, 2)))
+    for r in rows:
+        got = rho[int(r)].cpu().numpy()
+        ref = oracle.rho(n, e, np.full(d, r), np.arange(d))
+        assert np.max(np.abs(got - ref)) <= TOL, f"row {r}"
+    assert bool(torch.equal(rho, rho.conj().transpose(0, 1).contiguous()))
+    assert abs(torch.diagonal(rho).sum().item() - 1) <= TOL
+    _, rho32 = L.estimate(counts, shots, flags=L.LRE_RHO_FP32)
+    assert torch.equal(rho32, rho.to(torch.complex64))
+
+
 def test_no_rho_flag():
     counts = _haar_counts(6, 100, 61)
     coef, rho = L.estimate(_dev(counts), 100, flags=L.LRE_NO_RHO)
