@@ -72,16 +72,21 @@ class StageEvents:
                 self.hip.hipEventDestroy(ctypes.c_void_p(e))
 
 
-def measured_traffic(workload):
-    """HBM bytes per counts-pass launch from the committed rocprofv3 PMC summary, if it was
-    taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", f"traffic_fold_counts_{workload}.json")
+def measured_traffic(workload, tiles=None):
+    """HBM bytes per launch of the workload's dominant kernel (the counts pass; the batch
+    kernel for the batch) from the committed rocprofv3 PMC summary, if it was taken on the
+    current kernel source (and, for the batch, with the same work-item shape `tiles`);
+    else None."""
+    name = "batch_kernel_512_instances" if workload == "batch" else f"fold_counts_{workload}"
+    path = os.path.join(ROOT, "profiles", f"traffic_{name}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
     from paper_1602_08604_amd.profsum import kernel_source_hash
     if rec.get("kernel_source_hash") != kernel_source_hash(workload):
+        return None
+    if tiles is not None and f"--batch-tiles {tiles} " not in rec.get("command_fetch", ""):
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -592,7 +597,10 @@ def bench_batch(args, torch, lre):
                    "instances": 512, "n_histogram": hist, "total_counts": n_counts, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": 2.0 * n_counts / (ms_dev / 1e3) / 1e9, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": 2.0 * n_counts / (ms_dev / 1e3) / 1e9 / HBM_PEAK_GBS,
-                     "traffic": None, "kernel": "batch_kernel (persistent, all stages of all instances)",
+                     "traffic": None if args.no_rho else measured_traffic(
+                         "batch", ",".join(str(tiles[k]) for k in
+                                           ("workers_per_cu", "counts_tiles", "fold_cols", "rho_blocks", "interleave"))),
+                     "kernel": "batch_kernel (persistent, all stages of all instances)",
                      "algorithmic_bytes_per_launch": 2.0 * n_counts},
         "whole_step_hbm_frac": algo / (ms_dev / 1e3) / (HBM_PEAK_GBS * 1e9),
         "tiles": tiles, "tune_s": t_tune, "tuned_ms": tuned_ms,

@@ -1,6 +1,6 @@
 """Summaries of rocprofv3 output for the committed profile records.
 
-    python -m paper_1602_08604_amd.profsum stats   --dir D --out F.txt --command CMD
+    python -m paper_1602_08604_amd.profsum stats   --dir D --out F.txt --command CMD [--kernel REGEX]
     python -m paper_1602_08604_amd.profsum counters --dirs D... --commands CMD... --kernel REGEX --out F.txt
     python -m paper_1602_08604_amd.profsum traffic --fetch-dir D1 --write-dir D2 \
         --kernel REGEX --copy-kernel REGEX --copy-bytes B --out-json F.json --out-txt F.txt \
@@ -58,6 +58,8 @@ def _find(d: str, suffix: str) -> str:
 def stats(args):
     rows = list(csv.DictReader(open(_find(args.dir, "kernel_stats.csv"))))
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    if args.kernel:
+        rows = [r for r in rows if re.search(args.kernel, short_name(r["Name"]))]
     lines = [f"# rocprofv3 kernel statistics", "", f"command: {args.command}", "",
              f"{'kernel':72s} {'calls':>6s} {'avg_ms':>10s} {'min_ms':>10s} {'max_ms':>10s} {'pct':>6s}"]
     for r in rows[: args.top]:
@@ -172,6 +174,7 @@ def main():
     s.add_argument("--command", required=True)
     s.add_argument("--note", default="")
     s.add_argument("--top", type=int, default=14)
+    s.add_argument("--kernel", default="", help="keep only kernels matching this regex")
     t = sub.add_parser("traffic")
     t.add_argument("--fetch-dir", required=True)
     t.add_argument("--write-dir", required=True)
