@@ -599,7 +599,7 @@ def bench_batch(args, torch, lre):
                      "unit": "GB/s", "frac": 2.0 * n_counts / (ms_dev / 1e3) / 1e9 / HBM_PEAK_GBS,
                      "traffic": None if args.no_rho else measured_traffic(
                          "batch", ",".join(str(tiles[k]) for k in
-                                           ("workers_per_cu", "counts_tiles", "fold_cols", "rho_blocks", "interleave"))),
+                                           ("workers_per_cu", "counts_tiles", "fold_cols", "rho_blocks", "interleave", "staged"))),
                      "kernel": "batch_kernel (persistent, all stages of all instances)",
                      "algorithmic_bytes_per_launch": 2.0 * n_counts},
         "whole_step_hbm_frac": algo / (ms_dev / 1e3) / (HBM_PEAK_GBS * 1e9),
@@ -642,7 +642,7 @@ def main():
     ap.add_argument("--workload", default="n14", choices=["n14", "n12", "n8", "batch", "project", "stream15", "povm14"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-tiles", default="",
-                    help="batch workload: workers_per_cu,counts_tiles,fold_cols,rho_blocks,interleave "
+                    help="batch workload: workers_per_cu,counts_tiles,fold_cols,rho_blocks,interleave[,staged] "
                          "instead of running the autotuner")
     ap.add_argument("--no-rho", action="store_true",
                     help="batch workload: coefficients only (LRE_NO_RHO), to attribute step (ii)'s share")

@@ -169,12 +169,16 @@ lre_status lre_signed_sums(lre_ctx* ctx, int n, const uint16_t* counts, const in
  *
  * lre_batch_plan builds a work list (an instance of n <= 7 qubits is one item; a larger
  * one is split into its counts-pass row groups, later pass and step-(ii) blocks, in
- * dependency order) and uploads it.  lre_batch_run enqueues two kernels: a fill kernel that clears the
+ * dependency order) and uploads it.  lre_batch_run enqueues a fill kernel that clears the
  * item and dependency counters in the workspace, then one persistent kernel whose
  * workgroups take items from the list in order; an item that needs the results of
  * earlier items waits for their counters (a bounded wait: on expiry the item is
- * skipped and LRE_E_TIMEOUT is raised through lre_check).  lre_batch_run makes no
- * allocation, copy or memset and may be captured into a HIP graph.
+ * skipped and LRE_E_TIMEOUT is raised through lre_check).  For a plan with instances
+ * of more than 7 qubits it then enqueues the staged form's fold and step-(ii) kernels,
+ * which return at once unless the plan's shape is staged (lre_batch_tiles.staged), so
+ * that a captured run replays correctly after lre_batch_set_tiles or lre_batch_tune.
+ * lre_batch_run makes no allocation, copy or memset and may be captured into a HIP
+ * graph.
  */
 #define LRE_BATCH_MAX_QUBITS 9
 
@@ -205,6 +209,12 @@ typedef struct {
                            (2^(n-6) per instance of n > 7 qubits) */
   int interleave;       /* 0: stage by stage, largest instances first;
                            1: instance by instance (all stages of an instance together) */
+  int staged;           /* 0: every stage in the persistent kernel's work list;
+                           1: the list holds the per-basis totals, the counts pass and the
+                           instances of at most 7 qubits, and the later fold and step (ii)
+                           of the larger instances follow as two kernels of their own (one
+                           thread per column; one block per step-(ii) unit), in stream
+                           order; fold_cols, rho_blocks and interleave then do not matter */
 } lre_batch_tiles;
 
 typedef struct lre_batch lre_batch;
@@ -236,8 +246,9 @@ lre_status lre_batch_set_tiles(lre_batch* plan, const lre_batch_tiles* tiles);
 /* The plan's current work-item shape and work-item count. */
 lre_status lre_batch_get_tiles(const lre_batch* plan, lre_batch_tiles* tiles, int* num_items);
 
-/* Autotuner: runs the batch (lre_batch_run) for each of 72 candidate work-item shapes
- * (36 for a plan with per-basis instances, which run one workgroup per CU),
+/* Autotuner: runs the batch (lre_batch_run) for each of 82 candidate work-item shapes
+ * (72 unstaged and 10 staged; 41 for a plan with per-basis instances, which run one
+ * workgroup per CU),
  * `reps` timed runs each after one warm-up, keeps the fastest shape and returns its
  * mean time in *best_ms (may be NULL).  Synchronous on `stream`; overwrites the
  * instances' outputs.  workspace as for lre_batch_run. */

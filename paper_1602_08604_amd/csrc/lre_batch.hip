@@ -424,6 +424,58 @@ __global__ __launch_bounds__(kBT, WORKERS == 2 ? 4 : 1) void batch_kernel(
   }
 }
 
+// Staged form (lre_batch_tiles.staged = 1): the work list holds only the per-basis
+// totals, the counts pass and the instances of at most 7 qubits; the later fold and
+// step (ii) of the larger instances run afterwards, in stream order, as the two kernels
+// below, shaped for their own work (many small workgroups instead of one 7-wave worker
+// per CU).  Both read the plan's form from device memory (stage[1]) and do nothing for
+// an unstaged list, so that a captured launch stays valid whichever shape the plan
+// takes later.  Blocks are persistent (the grid is fixed when the plan is made) and
+// walk their work with a stride of the grid.
+
+// The later fold of every instance with n > 7: 4^7 columns per instance, 256 per block
+// (64 blocks per instance), one thread per column, the fold items' column function.
+template <bool PB>
+__global__ __launch_bounds__(256) void batch_fold_kernel(const int* __restrict__ stage,
+                                                         const int32_t* __restrict__ fold_inst, int nblocks,
+                                                         const BInst* __restrict__ insts, char* __restrict__ ws_arg) {
+  if (stage[1] == 0) return;
+  LRE_GLOBAL char* ws = (LRE_GLOBAL char*)ws_arg;
+  for (int b = blockIdx.x; b < nblocks; b += gridDim.x) {
+    const BInst& D = insts[fold_inst[b]];   // 64 consecutive blocks per instance
+    const BInstG I = global_view(D);
+    const int64_t col = ((int64_t)(b & 63) << 8) | threadIdx.x;
+    double* coef = (double*)I.coef;
+    const int F = I.n - kQ;
+    if (PB && I.shots == 0) {
+      const double* in = reinterpret_cast<const double*>(g2p(ws + I.off_part));
+      if (F == 1) fold_partial_col<1, double, double, Out::CoefPerBasis>(in, coef, I.n, 1, kQ, 0, col);
+      else fold_partial_col<2, double, double, Out::CoefPerBasis>(in, coef, I.n, 2, kQ, 0, col);
+    } else {
+      const uint32_t* in = reinterpret_cast<const uint32_t*>(g2p(ws + I.off_part));
+      if (F == 1) fold_partial_col<1, uint32_t, uint32_t, Out::CoefUniform>(in, coef, I.n, 1, kQ, I.shots, col);
+      else fold_partial_col<2, uint32_t, uint32_t, Out::CoefUniform>(in, coef, I.n, 2, kQ, I.shots, col);
+    }
+  }
+}
+
+// Step (ii) of every instance with n > 7: one rho_tiles unit (x_hi, 8 x_lo) per block.
+template <typename OutT>
+__global__ __launch_bounds__(256) void batch_rho_kernel(const int* __restrict__ stage, const int2* __restrict__ units,
+                                                        int nblocks, const BInst* __restrict__ insts) {
+  __shared__ double V[RhoTileGeom<3>::NV];
+  if (stage[1] == 0) return;
+  for (int b = blockIdx.x; b < nblocks; b += gridDim.x) {
+    const int2 w = units[b];
+    const BInstG I = global_view(insts[w.x]);
+    const double* coef = (const double*)I.coef;
+    void* rho = (void*)g2p(I.rho);
+    if (I.n == kJ + 2) rho_tiles<2, OutT, 256>(coef, rho, w.y, (int64_t)w.y + 1, threadIdx.x, V);
+    else rho_tiles<3, OutT, 256>(coef, rho, w.y, (int64_t)w.y + 1, threadIdx.x, V);
+    lds_barrier();  // the next unit's staging overwrites V
+  }
+}
+
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct InstMeta {
@@ -445,7 +497,11 @@ struct lre_batch {
   lre_batch_tiles tiles{};
   BInst* d_inst = nullptr;
   BItem* d_items = nullptr;     // work list, allocated once at the largest list any
-  int* d_nitems = nullptr;      // shape can give (fixed addresses for captured runs)
+  int* d_nitems = nullptr;      // shape can give (fixed addresses for captured runs);
+                                // [0] item count, [1] staged form
+  int32_t* d_fold = nullptr;    // staged form: instance of each fold block (64 per
+  int2* d_units = nullptr;      // instance of n > 7) and (instance, unit) of each rho block
+  int nfold = 0, nunits = 0;
   size_t items_cap = 0;
   int nitems = 0;
   size_t ctl_bytes = 0;
@@ -458,7 +514,8 @@ namespace {
 
 bool valid_tiles(const lre_batch_tiles& t) {
   return (t.workers_per_cu == 1 || t.workers_per_cu == 2) && t.counts_tiles >= 1 && t.fold_cols >= kBT &&
-         t.fold_cols % kBT == 0 && t.rho_blocks >= 1 && (t.interleave == 0 || t.interleave == 1);
+         t.fold_cols % kBT == 0 && t.rho_blocks >= 1 && (t.interleave == 0 || t.interleave == 1) &&
+         (t.staged == 0 || t.staged == 1);
 }
 
 void add_range(std::vector<BItem>& out, int inst, Kind kind, uint8_t var, int64_t total, int64_t per,
@@ -533,11 +590,20 @@ std::vector<BItem> list_items(const lre_batch& B, const lre_batch_tiles& t) {
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return B.meta[a].counts > B.meta[b].counts; });
   std::vector<BItem> items;
   std::vector<StageCounts> sc(count);
+  const int stages = t.staged ? 2 : kStages;   // staged: folds and step (ii) run as kernels of their own
   if (t.interleave) {
     for (int j : order)
-      for (int s = 0; s < kStages; ++s) emit_stage(B, t, j, s, items, sc[j]);
+      for (int s = 0; s < stages; ++s) emit_stage(B, t, j, s, items, sc[j]);
+  } else if (t.staged) {
+    // the long counts-pass items first, the one-item instances (n <= 7) after them to
+    // fill the end of the launch, largest first
+    for (int s = 0; s < stages; ++s)
+      for (int j : order)
+        if (B.meta[j].n > kQ) emit_stage(B, t, j, s, items, sc[j]);
+    for (int j : order)
+      if (B.meta[j].n <= kQ) emit_stage(B, t, j, 0, items, sc[j]);
   } else {
-    for (int s = 0; s < kStages; ++s)
+    for (int s = 0; s < stages; ++s)
       for (int j : order) emit_stage(B, t, j, s, items, sc[j]);
   }
   return items;
@@ -554,10 +620,34 @@ lre_status rebuild(lre_batch& B) {
   if (!items.empty() &&
       hipMemcpy(B.d_items, items.data(), items.size() * sizeof(BItem), hipMemcpyHostToDevice) != hipSuccess)
     return LRE_E_HIP;
-  const int cnt = (int)items.size();
-  if (hipMemcpy(B.d_nitems, &cnt, sizeof cnt, hipMemcpyHostToDevice) != hipSuccess) return LRE_E_HIP;
+  const int hdr[2] = {(int)items.size(), B.tiles.staged};
+  if (hipMemcpy(B.d_nitems, hdr, sizeof hdr, hipMemcpyHostToDevice) != hipSuccess) return LRE_E_HIP;
+  const int cnt = hdr[0];
   B.nitems = cnt;
   return LRE_OK;
+}
+
+// The staged form's fold and step-(ii) kernels (they return at once for an unstaged
+// list; see batch_fold_kernel).
+void launch_staged(const lre_batch& B, char* ws, hipStream_t st) {
+  if (B.nfold) {
+    const unsigned grid = (unsigned)std::min(B.nfold, B.num_cu * 8);
+    if (B.pb)
+      hipLaunchKernelGGL((batch_fold_kernel<true>), dim3(grid), dim3(256), 0, st, (const int*)B.d_nitems,
+                         (const int32_t*)B.d_fold, B.nfold, (const BInst*)B.d_inst, ws);
+    else
+      hipLaunchKernelGGL((batch_fold_kernel<false>), dim3(grid), dim3(256), 0, st, (const int*)B.d_nitems,
+                         (const int32_t*)B.d_fold, B.nfold, (const BInst*)B.d_inst, ws);
+  }
+  if (B.nunits) {
+    const unsigned grid = (unsigned)std::min(B.nunits, B.num_cu * 4);
+    if (B.flags & LRE_RHO_FP32)
+      hipLaunchKernelGGL((batch_rho_kernel<float>), dim3(grid), dim3(256), 0, st, (const int*)B.d_nitems,
+                         (const int2*)B.d_units, B.nunits, (const BInst*)B.d_inst);
+    else
+      hipLaunchKernelGGL((batch_rho_kernel<double>), dim3(grid), dim3(256), 0, st, (const int*)B.d_nitems,
+                         (const int2*)B.d_units, B.nunits, (const BInst*)B.d_inst);
+  }
 }
 
 }  // namespace
@@ -639,7 +729,7 @@ lre_status lre_batch_plan(lre_ctx* ctx, const lre_instance* inst, int count, uin
   }
   // The smallest shape (one row group, kBT columns, one row pattern per item) gives
   // the longest list; the list is allocated once at that length.
-  const size_t cap = list_items(*B, lre_batch_tiles{1, 1, kBT, 1, 0}).size();
+  const size_t cap = list_items(*B, lre_batch_tiles{1, 1, kBT, 1, 0, 0}).size();
   if (cap > (size_t)INT32_MAX) {
     lre_batch_destroy(B);
     return LRE_E_UNSUPPORTED;
@@ -650,7 +740,28 @@ lre_status lre_batch_plan(lre_ctx* ctx, const lre_instance* inst, int count, uin
     return LRE_E_HIP;
   }
   B->items_cap = cap;
-  B->tiles = lre_batch_tiles{1, 4, kBT * 16, 1, 0};
+  // staged form: fold blocks and step-(ii) units of the instances with n > 7
+  std::vector<int32_t> fold;
+  std::vector<int2> units;
+  for (int j = 0; j < count; ++j) {
+    if (B->meta[j].n <= kQ) continue;
+    for (int k = 0; k < 64; ++k) fold.push_back(j);
+    if (want_rho)
+      for (int u = 0; u < (8 << (B->meta[j].n - kJ)); ++u) units.push_back(make_int2(j, u));
+  }
+  B->nfold = (int)fold.size();
+  B->nunits = (int)units.size();
+  if ((B->nfold && hipMalloc(&B->d_fold, fold.size() * sizeof(int32_t)) != hipSuccess) ||
+      (B->nunits && hipMalloc(&B->d_units, units.size() * sizeof(int2)) != hipSuccess)) {
+    lre_batch_destroy(B);
+    return LRE_E_HIP;
+  }
+  if ((B->nfold && hipMemcpy(B->d_fold, fold.data(), fold.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) ||
+      (B->nunits && hipMemcpy(B->d_units, units.data(), units.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess)) {
+    lre_batch_destroy(B);
+    return LRE_E_HIP;
+  }
+  B->tiles = lre_batch_tiles{1, 4, kBT * 16, 1, 0, 0};
   const lre_status s = rebuild(*B);
   if (s != LRE_OK) {
     lre_batch_destroy(B);
@@ -690,6 +801,7 @@ lre_status lre_batch_run(lre_batch* plan, void* workspace, size_t workspace_byte
     hipLaunchKernelGGL((batch_kernel<1, true>), dim3((unsigned)plan->num_cu), dim3(kBT), 0, st,
                        (const BItem*)plan->d_items, (const int*)plan->d_nitems, (const BInst*)plan->d_inst, ws, ctl,
                        plan->ctx->flags);
+    launch_staged(*plan, ws, st);
     return hipGetLastError() == hipSuccess ? LRE_OK : LRE_E_HIP;
   }
   const int workers = plan->num_cu * plan->tiles.workers_per_cu;
@@ -699,6 +811,7 @@ lre_status lre_batch_run(lre_batch* plan, void* workspace, size_t workspace_byte
   else
     hipLaunchKernelGGL((batch_kernel<2, false>), dim3((unsigned)workers), dim3(kBT), 0, st, (const BItem*)plan->d_items,
                        (const int*)plan->d_nitems, (const BInst*)plan->d_inst, ws, ctl, plan->ctx->flags);
+  launch_staged(*plan, ws, st);
   return hipGetLastError() == hipSuccess ? LRE_OK : LRE_E_HIP;
 }
 
@@ -718,13 +831,18 @@ lre_status lre_batch_tune(lre_batch* plan, void* workspace, size_t workspace_byt
   lre_batch_tiles best = start;
   double best_t = 1e300;
   lre_status s = LRE_OK;
+  for (int sg : {0, 1})
   for (int w : {1, 2})
-    for (int ct : {1, 2, 4})
+    for (int ct : {1, 2, 4, 8, 16})
       for (int fc : {kBT * 4, kBT * 16})
         for (int rb : {1, 2, 4})
           for (int il : {0, 1}) {
             if (w == 2 && plan->pb) continue;  // per-basis plans run one workgroup per CU
-            const lre_batch_tiles t{w, ct, fc, rb, il};
+            // unstaged: 1, 2 or 4 row groups per counts item; staged: the fold and
+            // step-(ii) shapes are those of their own kernels
+            if (!sg && ct > 4) continue;
+            if (sg && (fc != kBT * 16 || rb != 1 || il != 0)) continue;
+            const lre_batch_tiles t{w, ct, fc, rb, il, sg};
             if ((s = lre_batch_set_tiles(plan, &t)) != LRE_OK) goto done;
             if ((s = lre_batch_run(plan, workspace, workspace_bytes, stream)) != LRE_OK) goto done;
             if (hipEventRecord(e0, st) != hipSuccess) { s = LRE_E_HIP; goto done; }
@@ -758,6 +876,8 @@ void lre_batch_destroy(lre_batch* plan) {
     if (plan->d_items) (void)hipFree(plan->d_items);
     if (plan->d_nitems) (void)hipFree(plan->d_nitems);
     if (plan->d_inst) (void)hipFree(plan->d_inst);
+    if (plan->d_fold) (void)hipFree(plan->d_fold);
+    if (plan->d_units) (void)hipFree(plan->d_units);
   }
   delete plan;
 }

@@ -44,7 +44,8 @@ class lre_instance(ctypes.Structure):
 
 class lre_batch_tiles(ctypes.Structure):
     _fields_ = [("workers_per_cu", ctypes.c_int), ("counts_tiles", ctypes.c_int),
-                ("fold_cols", ctypes.c_int), ("rho_blocks", ctypes.c_int), ("interleave", ctypes.c_int)]
+                ("fold_cols", ctypes.c_int), ("rho_blocks", ctypes.c_int), ("interleave", ctypes.c_int),
+                ("staged", ctypes.c_int)]
 
 
 class LreError(RuntimeError):
@@ -472,10 +473,10 @@ class Batch:
         _ok(lib().lre_batch_get_tiles(ctypes.c_void_p(self._h), ctypes.byref(t), ctypes.byref(k)),
             "lre_batch_get_tiles")
         return {"workers_per_cu": t.workers_per_cu, "counts_tiles": t.counts_tiles, "fold_cols": t.fold_cols,
-                "rho_blocks": t.rho_blocks, "interleave": t.interleave, "items": k.value}
+                "rho_blocks": t.rho_blocks, "interleave": t.interleave, "staged": t.staged, "items": k.value}
 
-    def set_tiles(self, workers_per_cu, counts_tiles, fold_cols, rho_blocks, interleave):
-        t = lre_batch_tiles(workers_per_cu, counts_tiles, fold_cols, rho_blocks, interleave)
+    def set_tiles(self, workers_per_cu, counts_tiles, fold_cols, rho_blocks, interleave, staged=0):
+        t = lre_batch_tiles(workers_per_cu, counts_tiles, fold_cols, rho_blocks, interleave, staged)
         _ok(lib().lre_batch_set_tiles(ctypes.c_void_p(self._h), ctypes.byref(t)), "lre_batch_set_tiles")
 
     def close(self):

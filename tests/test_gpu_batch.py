@@ -66,7 +66,8 @@ def test_batch_matches_single_and_oracle():
 
 
 @pytest.mark.parametrize("tiles", [(1, 1, 432, 1, 0), (2, 4, 432 * 16, 16, 1), (1, 3, 432 * 5, 7, 1),
-                                   (2, 1, 432, 8, 0)])
+                                   (2, 1, 432, 8, 0), (1, 4, 432 * 16, 1, 0, 1), (2, 1, 432, 1, 0, 1),
+                                   (1, 2, 432 * 4, 2, 1, 1)])
 def test_batch_tile_shapes(tiles):
     print(f"[batch tiles {tiles}]", flush=True)
     counts, shots = _instances(12, [9, 4, 8, 7, 1, 9, 6, 5])
@@ -77,14 +78,17 @@ def test_batch_tile_shapes(tiles):
     b.close()
 
 
-def test_batch_no_rho_and_fp32():
-    print("[batch NO_RHO / RHO_FP32]", flush=True)
+@pytest.mark.parametrize("staged", [0, 1])
+def test_batch_no_rho_and_fp32(staged):
+    print(f"[batch NO_RHO / RHO_FP32, staged={staged}]", flush=True)
     counts, shots = _instances(13, [9, 8, 5, 7, 3])
     b = L.Batch(counts, shots, flags=L.LRE_NO_RHO)
+    b.set_tiles(1, 4, 432 * 16, 1, 0, staged)
     b.run(check=True)
     _check_against_single(b, L.LRE_NO_RHO)
     b.close()
     b32 = L.Batch(counts, shots, flags=L.LRE_RHO_FP32)
+    b32.set_tiles(1, 4, 432 * 16, 1, 0, staged)
     b32.run(check=True)
     _check_against_single(b32, L.LRE_RHO_FP32)
     b64 = L.Batch(counts, shots)
@@ -166,13 +170,15 @@ def test_batch_errors():
     b.close()
 
 
-def test_batch_graph_survives_retune():
+@pytest.mark.parametrize("captured", [(1, 4, 432 * 16, 1, 0, 0), (1, 4, 432 * 16, 1, 0, 1)])
+def test_batch_graph_survives_retune(captured):
     """A launch captured before lre_batch_set_tiles replays the new work list (the list
-    keeps its address and the kernel reads the item count from device memory)."""
-    print("[batch graph + retune]", flush=True)
+    keeps its address and the kernels read the item count and the staged flag from
+    device memory), between the staged and unstaged forms too."""
+    print(f"[batch graph + retune, captured with {captured}]", flush=True)
     counts, shots = _instances(17, [9, 8, 9, 7, 4, 8])
     b = L.Batch(counts, shots)
-    b.set_tiles(1, 4, 432 * 16, 1, 0)
+    b.set_tiles(*captured)
     b.run(check=True)
     want_c = [c.clone() for c in b.coefs]
     want_r = [r.clone() for r in b.rhos]
@@ -187,7 +193,8 @@ def test_batch_graph_survives_retune():
     with torch.cuda.graph(g):
         b.run()
     items0 = b.tiles["items"]
-    for shape in ((1, 1, 432, 4, 1), (1, 2, 432 * 4, 2, 0), (1, 4, 432 * 16, 1, 0)):
+    for shape in ((1, 1, 432, 4, 1), (1, 2, 432 * 4, 2, 0, 1), (1, 2, 432 * 4, 2, 0), (2, 1, 432, 1, 0, 1),
+                  captured):
         b.set_tiles(*shape)
         print(f"  retuned to {b.tiles} (captured with {items0} items)", flush=True)
         for c in b.coefs:
@@ -245,11 +252,17 @@ def test_batch_per_basis():
                 [[0, 4 ** n - 1], np.random.default_rng(j).integers(0, 4 ** n, 300)])
             ref = oracle.coefs(n, host, 0, idx=idx)
             assert np.max(np.abs(e[idx] - ref)) <= TOL, f"instance {j}"
-        b.tune(reps=1)
-        b.run(check=True)
-        for j in range(len(ns)):
-            coef, _ = L.estimate(counts[j], shots[j], n_per_basis=nbs[j], flags=flags)
-            assert (b.coefs[j] - coef).abs().max().item() <= TOL
+        for shape in ("tuned", (1, 2, 432 * 16, 1, 0, 1)):
+            if shape == "tuned":
+                b.tune(reps=1)
+            else:
+                b.set_tiles(*shape)
+            b.run(check=True)
+            for j in range(len(ns)):
+                coef, rho = L.estimate(counts[j], shots[j], n_per_basis=nbs[j], flags=flags)
+                assert (b.coefs[j] - coef).abs().max().item() <= TOL, f"{shape}: instance {j}"
+                tol_r = TOL if flags == 0 else 1e-6
+                assert (b.rhos[j].to(torch.complex128) - rho.to(torch.complex128)).abs().max().item() <= tol_r
         b.close()
 
 
