@@ -600,7 +600,9 @@ def bench_batch(args, torch, lre):
                      "traffic": None if args.no_rho else measured_traffic(
                          "batch", ",".join(str(tiles[k]) for k in
                                            ("workers_per_cu", "counts_tiles", "fold_cols", "rho_blocks", "interleave", "staged"))),
-                     "kernel": "batch_kernel (persistent, all stages of all instances)",
+                     "kernel": ("batch launch: persistent batch_kernel (counts pass, instances of n <= 7), "
+                                "batch_fold_kernel, batch_rho_kernel" if tiles.get("staged") else
+                                "batch_kernel (persistent, all stages of all instances)"),
                      "algorithmic_bytes_per_launch": 2.0 * n_counts},
         "whole_step_hbm_frac": algo / (ms_dev / 1e3) / (HBM_PEAK_GBS * 1e9),
         "tiles": tiles, "tune_s": t_tune, "tuned_ms": tuned_ms,

@@ -3,7 +3,7 @@
     python -m paper_1602_08604_amd.profsum stats   --dir D --out F.txt --command CMD [--kernel REGEX]
     python -m paper_1602_08604_amd.profsum counters --dirs D... --commands CMD... --kernel REGEX --out F.txt
     python -m paper_1602_08604_amd.profsum traffic --fetch-dir D1 --write-dir D2 \
-        --kernel REGEX --copy-kernel REGEX --copy-bytes B --out-json F.json --out-txt F.txt \
+        --kernel REGEX [--sum-kernels] --copy-kernel REGEX --copy-bytes B --out-json F.json --out-txt F.txt \
         --command-fetch CMD1 --command-write CMD2
 
 `stats` turns a `rocprofv3 --kernel-trace --stats` kernel_stats CSV into a short text
@@ -95,11 +95,21 @@ def _pick(means, regex):
     return hits[0]
 
 
+def _sum_all(means, regex):
+    """Every kernel matching regex, summed per dispatch (kernels launched once each per
+    step of a multi-kernel launch)."""
+    hits = sorted((k, v) for k, v in means.items() if re.search(regex, k))
+    if not hits:
+        raise SystemExit(f"no kernel matches {regex!r}; have {sorted(means)}")
+    return " + ".join(k for k, _ in hits), (sum(v[0] for _, v in hits), min(v[1] for _, v in hits))
+
+
 def traffic(args):
     fetch = _counter_means(args.fetch_dir, "FETCH_SIZE")
     write = _counter_means(args.write_dir, "WRITE_SIZE")
-    kname, (f_kib, f_n) = _pick(fetch, args.kernel)
-    _, (w_kib, w_n) = _pick(write, args.kernel)
+    pick = _sum_all if args.sum_kernels else _pick
+    kname, (f_kib, f_n) = pick(fetch, args.kernel)
+    _, (w_kib, w_n) = pick(write, args.kernel)
     cname, (cf_kib, _) = _pick(fetch, args.copy_kernel)
     _, (cw_kib, _) = _pick(write, args.copy_kernel)
     f_read = args.copy_bytes / (cf_kib * 1024.0)
@@ -179,6 +189,8 @@ def main():
     t.add_argument("--fetch-dir", required=True)
     t.add_argument("--write-dir", required=True)
     t.add_argument("--kernel", required=True)
+    t.add_argument("--sum-kernels", action="store_true",
+                   help="sum every kernel matching --kernel (one launch made of several kernels)")
     t.add_argument("--copy-kernel", required=True)
     t.add_argument("--copy-bytes", type=float, required=True)
     t.add_argument("--workload", required=True)
