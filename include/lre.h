@@ -174,7 +174,7 @@ lre_status lre_signed_sums(lre_ctx* ctx, int n, const uint16_t* counts, const in
  * workgroups take items from the list in order; an item that needs the results of
  * earlier items waits for their counters (a bounded wait: on expiry the item is
  * skipped and LRE_E_TIMEOUT is raised through lre_check).  For a plan with instances
- * of more than 7 qubits it then enqueues the staged form's fold and step-(ii) kernels,
+ * of 7 or more qubits it then enqueues the staged form's fold and step-(ii) kernels,
  * which return at once unless the plan's shape is staged (lre_batch_tiles.staged), so
  * that a captured run replays correctly after lre_batch_set_tiles or lre_batch_tune.
  * lre_batch_run makes no allocation, copy or memset and may be captured into a HIP
@@ -211,10 +211,11 @@ typedef struct {
                            1: instance by instance (all stages of an instance together) */
   int staged;           /* 0: every stage in the persistent kernel's work list;
                            1: the list holds the per-basis totals, the counts pass and the
-                           instances of at most 7 qubits, and the later fold and step (ii)
-                           of the larger instances follow as two kernels of their own (one
-                           thread per column; one block per step-(ii) unit), in stream
-                           order; fold_cols, rho_blocks and interleave then do not matter */
+                           instances of at most 7 qubits (step (ii) of those of exactly 7
+                           excepted), and the later fold and step (ii) follow as two
+                           kernels of their own (one thread per column; one block per
+                           step-(ii) unit), in stream order; fold_cols, rho_blocks and
+                           interleave then do not matter */
 } lre_batch_tiles;
 
 typedef struct lre_batch lre_batch;

@@ -425,9 +425,9 @@ __global__ __launch_bounds__(kBT, WORKERS == 2 ? 4 : 1) void batch_kernel(
 }
 
 // Staged form (lre_batch_tiles.staged = 1): the work list holds only the per-basis
-// totals, the counts pass and the instances of at most 7 qubits; the later fold and
-// step (ii) of the larger instances run afterwards, in stream order, as the two kernels
-// below, shaped for their own work (many small workgroups instead of one 7-wave worker
+// totals, the counts pass and the instances of at most 7 qubits (those of exactly 7
+// without their step (ii)); the later fold and step (ii) run afterwards, in stream
+// order, as the two kernels below, shaped for their own work (many small workgroups instead of one 7-wave worker
 // per CU).  Both read the plan's form from device memory (stage[1]) and do nothing for
 // an unstaged list, so that a captured launch stays valid whichever shape the plan
 // takes later.  Blocks are persistent (the grid is fixed when the plan is made) and
@@ -459,7 +459,7 @@ __global__ __launch_bounds__(256) void batch_fold_kernel(const int* __restrict__
   }
 }
 
-// Step (ii) of every instance with n > 7: one rho_tiles unit (x_hi, 8 x_lo) per block.
+// Step (ii) of every instance with n >= 7: one rho_tiles unit (x_hi, 8 x_lo) per block.
 template <typename OutT>
 __global__ __launch_bounds__(256) void batch_rho_kernel(const int* __restrict__ stage, const int2* __restrict__ units,
                                                         int nblocks, const BInst* __restrict__ insts) {
@@ -470,7 +470,8 @@ __global__ __launch_bounds__(256) void batch_rho_kernel(const int* __restrict__ 
     const BInstG I = global_view(insts[w.x]);
     const double* coef = (const double*)I.coef;
     void* rho = (void*)g2p(I.rho);
-    if (I.n == kJ + 2) rho_tiles<2, OutT, 256>(coef, rho, w.y, (int64_t)w.y + 1, threadIdx.x, V);
+    if (I.n == kJ + 1) rho_tiles<1, OutT, 256>(coef, rho, w.y, (int64_t)w.y + 1, threadIdx.x, V);
+    else if (I.n == kJ + 2) rho_tiles<2, OutT, 256>(coef, rho, w.y, (int64_t)w.y + 1, threadIdx.x, V);
     else rho_tiles<3, OutT, 256>(coef, rho, w.y, (int64_t)w.y + 1, threadIdx.x, V);
     lds_barrier();  // the next unit's staging overwrites V
   }
@@ -558,8 +559,10 @@ void emit_stage(const lre_batch& B, const lre_batch_tiles& t, int j, int stage, 
   const uint8_t pb = m.pb ? V_PB : 0;
   const int32_t c_counts = 1 + 3 * j, c_fold = 2 + 3 * j, c_tot = 3 + 3 * j;
   if (m.n <= kQ) {  // one tile: the whole instance is one item
+    // (staged: step (ii) of a 7-qubit instance runs in the step-(ii) kernel instead)
+    const bool rho_here = want_rho && !(t.staged && m.n == kQ);
     if (stage == 0)
-      add_range(out, j, K_SMALL, (uint8_t)(mad | fp32 | pb | (want_rho ? V_RHO : 0)), 1, 1, -1, 0, -1, nullptr);
+      add_range(out, j, K_SMALL, (uint8_t)(mad | fp32 | pb | (rho_here ? V_RHO : 0)), 1, 1, -1, 0, -1, nullptr);
     return;
   }
   switch (stage) {
@@ -744,8 +747,9 @@ lre_status lre_batch_plan(lre_ctx* ctx, const lre_instance* inst, int count, uin
   std::vector<int32_t> fold;
   std::vector<int2> units;
   for (int j = 0; j < count; ++j) {
-    if (B->meta[j].n <= kQ) continue;
-    for (int k = 0; k < 64; ++k) fold.push_back(j);
+    if (B->meta[j].n < kQ) continue;
+    if (B->meta[j].n > kQ)
+      for (int k = 0; k < 64; ++k) fold.push_back(j);
     if (want_rho)
       for (int u = 0; u < (8 << (B->meta[j].n - kJ)); ++u) units.push_back(make_int2(j, u));
   }

@@ -78,6 +78,19 @@ def test_batch_tile_shapes(tiles):
     b.close()
 
 
+@pytest.mark.parametrize("ns", [[3, 5, 7, 1], [8], [9, 9], [7, 8]])
+def test_batch_staged_edge_sets(ns):
+    """The staged form with no later stage at all (every instance of at most 7 qubits),
+    with only one size of larger instance, and mixed."""
+    print(f"[batch staged {ns}]", flush=True)
+    counts, shots = _instances(21, ns)
+    b = L.Batch(counts, shots)
+    b.set_tiles(1, 4, 432 * 16, 1, 0, 1)
+    b.run(check=True)
+    _check_against_single(b)
+    b.close()
+
+
 @pytest.mark.parametrize("staged", [0, 1])
 def test_batch_no_rho_and_fp32(staged):
     print(f"[batch NO_RHO / RHO_FP32, staged={staged}]", flush=True)
