@@ -747,8 +747,9 @@ def bench_estimate(workload, args, torch, lre, extras):
     ms_step = head["ms_step"]
     pass1, step_i, step_ii = head["pass1"], head["step_i"], head["step_ii"]
     graph = None
-    if n <= 10:
-        # launch-bound sizes: the same step captured into a HIP graph and replayed
+    if n <= 12:
+        # the same step captured into a HIP graph and replayed (no launch gaps between
+        # its kernels; the lines' value stays the eager rate)
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(side):
