@@ -169,7 +169,18 @@ __device__ __noinline__ void run_totals(const BInstG& I, const BInstPB& X, int64
       N = X.nb_in[b];
     } else {
       uint32_t sum = 0;
-      for (int64_t o = lam; o < d; o += 16) sum += I.counts[b * d + o];
+      if (I.n >= 3) {
+        // 16-byte loads of 8 counts (rows of 2^n >= 8 counts start 16-byte aligned)
+        typedef uint32_t u32x4_v __attribute__((ext_vector_type(4)));
+        const LRE_GLOBAL u32x4_v* row = (const LRE_GLOBAL u32x4_v*)(I.counts + b * d);
+        for (int64_t o = lam; o < d / 8; o += 16) {
+          const u32x4_v v = row[o];
+          sum += (v.x & 0xFFFFu) + (v.x >> 16) + (v.y & 0xFFFFu) + (v.y >> 16) + (v.z & 0xFFFFu) + (v.z >> 16) +
+                 (v.w & 0xFFFFu) + (v.w >> 16);
+        }
+      } else {
+        for (int64_t o = lam; o < d; o += 16) sum += I.counts[b * d + o];
+      }
 #pragma unroll
       for (int o = 8; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 16);
       N = sum;

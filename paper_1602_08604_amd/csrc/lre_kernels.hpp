@@ -1224,7 +1224,17 @@ static __global__ __launch_bounds__(256) void row_totals_kernel(const uint16_t* 
   const int64_t d = (int64_t)1 << n;
   const uint16_t* row = counts + b * d;
   uint32_t s = 0;
-  for (int64_t i = threadIdx.x; i < d; i += 256) s += row[i];
+  if (n >= 3) {
+    // 16-byte loads of 8 counts (rows of 2^n >= 8 counts start 16-byte aligned)
+    for (int64_t i = (int64_t)threadIdx.x * 8; i < d; i += 256 * 8) {
+      typedef uint32_t u32x4_v __attribute__((ext_vector_type(4)));
+      const u32x4_v v = __builtin_nontemporal_load(reinterpret_cast<const u32x4_v*>(row + i));
+      s += (v.x & 0xFFFFu) + (v.x >> 16) + (v.y & 0xFFFFu) + (v.y >> 16) + (v.z & 0xFFFFu) + (v.z >> 16) +
+           (v.w & 0xFFFFu) + (v.w >> 16);
+    }
+  } else {
+    for (int64_t i = threadIdx.x; i < d; i += 256) s += row[i];
+  }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
   __shared__ uint32_t part[4];
