@@ -406,10 +406,8 @@ void launch_rho(const Plan& P, const double* coef, void* rho, char* ws, hipStrea
   const int64_t nblk = ipow4(n - kRhoJ);
   const int64_t low_blocks = std::min<int64_t>(nblk, resident_blocks(rho_low6_kernel, 256, 4096 * 8));
   hipLaunchKernelGGL(rho_low6_kernel, dim3((unsigned)low_blocks), dim3(256), 0, st, coef, tmp, nblk);
-  // 5..9 high qubits: two register phases with one LDS transpose
+  // 7..9 high qubits: two register phases with one LDS transpose
   switch (n - kRhoJ) {
-    case 5: launch_rho_high2<5, OutT>(tmp, rho, n, st); break;
-    case 6: launch_rho_high2<6, OutT>(tmp, rho, n, st); break;
     case 7: launch_rho_high2<7, OutT>(tmp, rho, n, st); break;
     case 8: launch_rho_high2<8, OutT>(tmp, rho, n, st); break;
     default: launch_rho_high2<9, OutT>(tmp, rho, n, st); break;   // n = 15 (streamed estimates)

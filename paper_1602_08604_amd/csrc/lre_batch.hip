@@ -163,33 +163,61 @@ __device__ __noinline__ void run_totals(const BInstG& I, const BInstPB& X, int64
   constexpr int kGroups = kBT / 16;
   const int grp = tid / 16, lam = tid % 16;
   const int64_t d = (int64_t)1 << I.n;
-  for (int64_t b = b0 + grp; b < b1; b += kGroups) {   // uniform within a group
-    uint32_t N;
-    if (X.nb_in) {
-      N = X.nb_in[b];
-    } else {
-      uint32_t sum = 0;
-      if (I.n >= 3) {
-        // 16-byte loads of 8 counts (rows of 2^n >= 8 counts start 16-byte aligned)
-        typedef uint32_t u32x4_v __attribute__((ext_vector_type(4)));
-        const LRE_GLOBAL u32x4_v* row = (const LRE_GLOBAL u32x4_v*)(I.counts + b * d);
-        for (int64_t o = lam; o < d / 8; o += 16) {
-          const u32x4_v v = row[o];
-          sum += (v.x & 0xFFFFu) + (v.x >> 16) + (v.y & 0xFFFFu) + (v.y >> 16) + (v.z & 0xFFFFu) + (v.z >> 16) +
-                 (v.w & 0xFFFFu) + (v.w >> 16);
-        }
-      } else {
-        for (int64_t o = lam; o < d; o += 16) sum += I.counts[b * d + o];
-      }
-#pragma unroll
-      for (int o = 8; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 16);
-      N = sum;
-    }
+  auto put = [&](int64_t b, uint32_t N) __attribute__((always_inline)) {
     if (lam == 0) {
       nb[b] = N;
       inv[b] = N ? 1.0 / (double)N : 0.0;
       if (!N) atomicOr(flags, (uint32_t)FLAG_EMPTY);
     }
+  };
+  if (X.nb_in) {
+    for (int64_t b = b0 + grp; b < b1; b += kGroups) put(b, X.nb_in[b]);
+    return;
+  }
+  if (I.n < 3) {
+    for (int64_t b = b0 + grp; b < b1; b += kGroups) {   // uniform within a group
+      uint32_t sum = 0;
+      for (int64_t o = lam; o < d; o += 16) sum += I.counts[b * d + o];
+#pragma unroll
+      for (int o = 8; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 16);
+      put(b, sum);
+    }
+    return;
+  }
+  // Rows of 2^n >= 8 counts start 16-byte aligned: 16-byte loads of 8 counts, kR rows
+  // per group at a time with all their loads issued before any is summed (a row of
+  // 2^n <= 512 counts is at most 4 loads per lane).
+  typedef uint32_t u32x4_v __attribute__((ext_vector_type(4)));
+  constexpr int kW = (1 << LRE_BATCH_MAX_QUBITS) / 8 / 16, kR = 4;
+  const int64_t words = d / 8;
+  auto hsum = [](const u32x4_v& v) __attribute__((always_inline)) {
+    return (v.x & 0xFFFFu) + (v.x >> 16) + (v.y & 0xFFFFu) + (v.y >> 16) + (v.z & 0xFFFFu) + (v.z >> 16) +
+           (v.w & 0xFFFFu) + (v.w >> 16);
+  };
+  for (int64_t b = b0 + grp; b < b1; b += kR * kGroups) {   // uniform within a group
+    u32x4_v w[kR][kW];
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+      const int64_t br = b + (int64_t)r * kGroups;
+      const LRE_GLOBAL u32x4_v* row = (const LRE_GLOBAL u32x4_v*)(I.counts + br * d);
+#pragma unroll
+      for (int k = 0; k < kW; ++k) {
+        const int64_t o = lam + 16 * k;
+        w[r][k] = (br < b1 && o < words) ? row[o] : u32x4_v{0u, 0u, 0u, 0u};
+      }
+    }
+    uint32_t sum[kR];
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+      sum[r] = 0;
+#pragma unroll
+      for (int k = 0; k < kW; ++k) sum[r] += hsum(w[r][k]);
+#pragma unroll
+      for (int o = 8; o > 0; o >>= 1) sum[r] += __shfl_xor(sum[r], o, 16);
+    }
+#pragma unroll
+    for (int r = 0; r < kR; ++r)
+      if (b + (int64_t)r * kGroups < b1) put(b + (int64_t)r * kGroups, sum[r]);
   }
 }
 

@@ -1226,6 +1226,7 @@ static __global__ __launch_bounds__(256) void row_totals_kernel(const uint16_t* 
   uint32_t s = 0;
   if (n >= 3) {
     // 16-byte loads of 8 counts (rows of 2^n >= 8 counts start 16-byte aligned)
+#pragma unroll 4
     for (int64_t i = (int64_t)threadIdx.x * 8; i < d; i += 256 * 8) {
       typedef uint32_t u32x4_v __attribute__((ext_vector_type(4)));
       const u32x4_v v = __builtin_nontemporal_load(reinterpret_cast<const u32x4_v*>(row + i));
@@ -1883,7 +1884,7 @@ __global__ __launch_bounds__(512) void rho_real_tile_kernel(const double* __rest
   rho_real_units<H, JB, OutT, 512>(coef, rho, blockIdx.x, gridDim.x, threadIdx.x, V);
 }
 
-// High transform for H = n - 6 in [5, 8] high qubits, 256 threads.  Block -> (x_hi, r_lo,
+// High transform for H = n - 6 in [7, 9] high qubits, 256 threads.  Block -> (x_hi, r_lo,
 // block of XB consecutive x_lo).  z = zA + 16 zB: phase A transforms zA (4 bits) in
 // registers per (x_lo, zB) and stores to LDS; phase B transforms zB (H - 4 bits) in
 // registers per (x_lo, zA) and writes rows r_hi = zA' + 16 zB' of mu.
