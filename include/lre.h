@@ -385,7 +385,7 @@ lre_status lre_stream_read(const void* buf, size_t bytes, uint32_t* sink, void* 
 lre_status lre_stream_copy(const void* src, void* dst, size_t bytes, void* stream);
 
 /* Compute issue rates (diagnostics, not part of the method), next to the datasheet
- * peaks the counts pass is judged against.  Each launches one kernel of `iters`
+ * peaks the counts pass is compared with.  Each launches one kernel of `iters`
  * iterations on `stream` (time it with events around the call) and stores in *ops
  * (host pointer, may be NULL) the number of operations the launch performs:
  *   lre_peak_valu_i32 : 32-bit integer adds, 8 independent chains per lane;

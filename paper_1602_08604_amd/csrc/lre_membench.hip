@@ -2,7 +2,7 @@
 //
 // Not part of the method: these two entry points measure what plain streaming kernels
 // reach on this device, the practical ceiling against which the estimator's kernels
-// (HBM-bound, 16-byte vector accesses) are judged next to the datasheet peak.
+// (HBM-bound, 16-byte vector accesses) are compared, beside the datasheet peak.
 #include <hip/hip_runtime.h>
 
 #include "lre.h"
