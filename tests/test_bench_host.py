@@ -41,3 +41,22 @@ def test_cpu_baseline_n14_all_cores_and_one():
     one = out["one_core"]
     assert one["cores"] == 1 and one["value"] > 0
     assert "threads" in out["sample"] and "1 thread" in one["sample"]
+
+
+def test_traffic_record_is_gated_by_source_hash_and_batch_shape(monkeypatch):
+    """bench.py reports a committed HBM-traffic record only while the kernel sources hash
+    to the recorded value and, for the batch, only for the work-item shape it was taken
+    with."""
+    import json
+    import re
+    from paper_1602_08604_amd import profsum
+    with open(os.path.join(ROOT, "profiles", "traffic_batch_kernel_512_instances.json")) as f:
+        rec = json.load(f)
+    tiles = re.search(r"--batch-tiles (\S+) ", rec["command_fetch"]).group(1)
+    monkeypatch.setattr(profsum, "kernel_source_hash", lambda workload="": rec["kernel_source_hash"])
+    assert bench.measured_traffic("batch", tiles) == rec["hbm_bytes_per_launch"]
+    other = ",".join(str(int(v) + (1 if k == 1 else 0)) for k, v in enumerate(tiles.split(",")))
+    assert bench.measured_traffic("batch", other) is None
+    monkeypatch.setattr(profsum, "kernel_source_hash", lambda workload="": "0" * 16)
+    assert bench.measured_traffic("batch", tiles) is None
+    assert bench.measured_traffic("n14") is None
