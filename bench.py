@@ -21,6 +21,7 @@ import ctypes
 import json
 import math
 import os
+import statistics
 import sys
 import time
 
@@ -725,7 +726,8 @@ def bench_estimate(workload, args, torch, lre, extras):
         res = {"ms_step": (t1 - t0) * 1e3 / args.steps,
                "pass1": [ev.ms(k, 0, 1) for k in range(args.steps)],
                "step_i": [ev.ms(k, 0, 2) for k in range(args.steps)],
-               "step_ii": [ev.ms(k, 2, 3) for k in range(args.steps)]}
+               "step_ii": [ev.ms(k, 2, 3) for k in range(args.steps)],
+               "whole": [ev.ms(k, 0, 3) for k in range(args.steps)]}
         ev.close()
         mean = lambda v: sum(v) / len(v)
         print(f"[bench] {workload} flags={flags}: {args.steps} steps: {res['ms_step']:.3f} ms/step wall; counts pass "
@@ -774,6 +776,26 @@ def bench_estimate(workload, args, torch, lre, extras):
         print(f"[bench] {workload}: graph replay {graph['ms_per_step']:.4f} ms/step", file=sys.stderr, flush=True)
         del g
 
+    cold = None
+    if n <= 8:
+        # cold caches: a 512 MB buffer touched before each timed call
+        flush = torch.empty(1 << 27, dtype=torch.float32, device="cuda:0")
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        cold_ms = []
+        for _ in range(max(args.steps, 5)):
+            flush.fill_(1.0)
+            torch.cuda.synchronize()
+            e0.record()
+            lre.estimate(counts, shots, n_per_basis=nb, coef=coef, rho=rho, workspace=ws, flags=head_flags,
+                         check=False)
+            e1.record()
+            torch.cuda.synchronize()
+            cold_ms.append(e0.elapsed_time(e1))
+        lre.check_flags("cuda:0")
+        del flush
+        cold = {"median_ms": statistics.median(cold_ms), "min_ms": min(cold_ms),
+                "how": "512 MB buffer written before each call; events around the call"}
+
     n_counts = 3 ** n * d
     t_pass1 = sum(pass1) / len(pass1) / 1e3
     achieved = 2.0 * n_counts / t_pass1 / 1e9
@@ -805,6 +827,12 @@ def bench_estimate(workload, args, torch, lre, extras):
         "wht": "int8-mfma" if head_flags else "plain-int32",
         "mfma_vs_plain": None,
     }
+    out["device_ms"] = {
+        "whole_step": {"median": statistics.median(head["whole"]), "min": min(head["whole"])},
+        "counts_pass": {"median": statistics.median(pass1), "min": min(pass1)},
+        "how": "HIP events the library records at stage boundaries, per timed step"}
+    if cold is not None:
+        out["cold_cache"] = cold
     if graph is not None:
         out["graph_replay"] = graph
     if other is not None:
