@@ -634,6 +634,7 @@ def bench_batch(args, torch, lre):
     b.close()
     out["hbm_measured"] = measured_hbm(torch, lre)
     out["compute_measured"] = measured_compute(torch, lre)
+    out["roofline"]["frac_of_measured_read"] = out["roofline"]["achieved"] / out["hbm_measured"]["stream_read_gbs"]
     print(json.dumps(out), flush=True)
 
 
@@ -859,6 +860,8 @@ def bench_estimate(workload, args, torch, lre, extras):
         torch.cuda.empty_cache()
         out["hbm_measured"] = measured_hbm(torch, lre)
         out["compute_measured"] = measured_compute(torch, lre)
+        # the counts pass against the device's measured streaming-read rate as well
+        out["roofline"]["frac_of_measured_read"] = achieved / out["hbm_measured"]["stream_read_gbs"]
     return out
 
 
