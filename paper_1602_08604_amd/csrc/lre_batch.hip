@@ -13,7 +13,9 @@
 // its output, releases it and bumps its stage's counter.  Items are taken in list
 // order by running workgroups, so every item waited for has already been taken by a
 // running workgroup and every wait ends; the wait is bounded anyway (FLAG_WAIT) so
-// that no wave can spin forever.
+// that no wave can spin forever.  In the staged form the list stops after the counts
+// pass and two kernels of their own run the later folds and step (ii) (see
+// batch_fold_kernel).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
